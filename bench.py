@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark: batched evaluation of the static autotuning model on one MI355X.
+
+One step = one pass of the whole hot path (occupancy, score and per-variant
+top-8 selection, with occupancy and score written out) over the batch of
+1,000 kernel variants x 16,384 launch configurations (block x unroll x
+registers x grid, 16,384,000 evaluations), inputs resident in HBM.
+
+Prints ONE JSON line (rank 0):
+  value        configurations scored per second (whole job)
+  roofline     the evaluation kernel against MI355X HBM peak (8 TB/s):
+               algorithmic bytes = 24 B per evaluation (16 B of configuration
+               columns read, 4 B occupancy + 4 B score written)
+  cpu_baseline the CPU oracle (binary32 mode + top-8) on the host cores, over
+               repetitions of the same workload for ~10 s
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "configs scored/sec, plain vs MLP-corrected; top-1 regret vs measured runtime"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_EVAL = 24
+K = 8
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU-baseline leg")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c1.json"),
+                   help="JSON with measured HBM bytes per launch of the evaluation kernel")
+    return p.parse_args()
+
+
+def cpu_baseline(batch, seconds: float) -> dict:
+    import oracle
+
+    arch = oracle.arch_cdna4()
+    nt = oracle.max_threads()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.run(arch, batch.variants, batch.configs(), k=K, want_occ=True, want_f32=True, want_f64=False,
+                   nthreads=nt)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": reps * batch.n_evals / dt, "unit": "configs/s", "cores": nt, "kind": "oracle",
+            "sample": "%d pass(es) over the full workload (%d evaluations each), binary32 scores + occupancy + "
+                      "top-%d, %.1f s" % (reps, batch.n_evals, K, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the model's batch shards by variant with no "
+              "exchange but the top-k gather; see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1701_08547_amd import api, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    arch = api.arch_default(0)
+    batch = workloads.c1(n_cu=arch["n_cu"])
+    var, cfg = api.device_batch(batch, dev)
+    n_var, n_evals = batch.n_var, batch.n_evals
+    outs = {
+        "occ": torch.empty(n_evals, dtype=torch.int32, device=dev),
+        "score": torch.empty(n_evals, dtype=torch.float32, device=dev),
+        "idx": torch.empty((n_var, K), dtype=torch.int32, device=dev),
+        "val": torch.empty((n_var, K), dtype=torch.float32, device=dev),
+    }
+    ws = api.Workspace(api.workspace_bytes(n_var, n_evals, K), dev)
+
+    def step():
+        api.score(arch, var, cfg, k=K, outputs=outs, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    mean_ms = sum(per_launch_ms) / len(per_launch_ms)
+    ms_per_step = wall * 1e3 / args.steps
+
+    value = n_evals * args.steps / wall
+    achieved = BYTES_PER_EVAL * n_evals / (mean_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain static model, 1000 variants x 16384 configs (block x unroll x regs x grid), "
+                        "occupancy + score written, top-8 per variant",
+            "n_variants": n_var,
+            "n_evals": n_evals,
+            "k": K,
+            "mode": "plain",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "sa_eval_kernel + sa_merge_kernel per step (HIP events per step)",
+            "event_ms_mean": mean_ms,
+            "event_ms_median": per_launch_ms[len(per_launch_ms) // 2],
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * sa.h -- C ABI of the MI355X (gfx950) static autotuning model.
+ *
+ * The library evaluates the static performance model of Lim, Norris and
+ * Malony, "Autotuning GPU Kernels via Static and Predictive Analysis"
+ * (arXiv:1701.08547) over batches of (kernel variant, launch configuration)
+ * pairs, on the GPU:
+ *
+ *   occupancy  Sec. III-A, Eqs. 1-5: the active blocks B* per compute unit are
+ *              the minimum of the wave-slot, register-file and shared-memory
+ *              (LDS) bounds; the active waves are W* = B* x W_B (Eq. 2).
+ *   score      Sec. III-B, Eq. 6: the instruction-mix cost
+ *              c_f O_fl + c_m O_mem + c_b O_ctrl + c_r O_reg, weighted by
+ *              branch divergence (Sec. II-A) and by a latency-hiding and
+ *              grid-tail factor (occupancy is not to be used alone, Eq. 2
+ *              discussion).
+ *   selection  Sec. II-C / III-C: per variant, the k configurations with the
+ *              smallest predicted cost (the autotuner keeps the fastest).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named in the argument structs and arrays are DEVICE pointers
+ *     (hipMalloc'd or torch CUDA tensors), owned by the caller; the library
+ *     never allocates, frees or retains them.  `sa_arch`, `sa_variants`,
+ *     `sa_configs` themselves are host structs read during the call.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously on it; results are valid after the stream synchronises.
+ *     No entry point synchronises, allocates or copies to the host, so calls
+ *     can be captured into a HIP graph.
+ *   - Argument errors (NULL required pointer, negative sizes, misalignment,
+ *     k outside [1, 64], too small a workspace, an unsupported descriptor)
+ *     return a negative status before anything is enqueued;
+ *     `sa_last_error()` then holds a message (per calling thread).
+ *   - Element values are never errors: an out-of-range configuration or
+ *     variant is "illegal" (occupancy 0, score +inf, never selected); see
+ *     `sa_configs` and `sa_variants`.  Segment offsets that are not
+ *     non-decreasing, or whose last entry differs from n_evals, give
+ *     unspecified results but every memory access stays in bounds.
+ *   - Layouts are structure-of-arrays; all int32/float arrays must be 4-byte
+ *     aligned, int64 arrays 8-byte aligned, the workspace 256-byte aligned.
+ */
+#ifndef SA_H_
+#define SA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sa_status;
+#define SA_OK 0
+#define SA_ERR_ARG (-1)         /* bad argument value or NULL required pointer */
+#define SA_ERR_ALIGN (-2)       /* pointer not aligned as required            */
+#define SA_ERR_NODEV (-3)       /* no HIP device visible                      */
+#define SA_ERR_WORKSPACE (-4)   /* workspace missing or smaller than needed   */
+#define SA_ERR_HIP (-5)         /* a HIP runtime call failed                  */
+#define SA_ERR_UNSUPPORTED (-6) /* descriptor or option outside what is built */
+
+#define SA_K_MAX 64
+
+/*
+ * Target descriptor (the paper's Table I limits and Table II weights).
+ * One descriptor describes both the paper's NVIDIA parts (one register pool
+ * per SM) and CDNA parts (`simd_per_cu` register-file partitions).
+ *
+ * Occupancy of a launch with T threads, R registers per thread and S bytes of
+ * LDS per block (W_B = ceil(T / wave_size) waves per block):
+ *   G_W = min(B_lim, floor(max_waves_per_cu / W_B))         (Eq. 3)
+ *         B_lim = max_blocks_per_cu, unlimited when W_B = 1 and
+ *         single_wave_exempt != 0
+ *   G_R = floor(simd_per_cu * w_v / W_B),                    (Eq. 4, plain reading)
+ *         w_v = min(max_waves_per_cu / simd_per_cu,
+ *                   floor(vgprs_per_simd_lane / roundup(R, vgpr_granule)));
+ *         unlimited when R = 0
+ *   G_S = floor(lds_per_cu / roundup(S, lds_granule)),       (Eq. 5, floor)
+ *         unlimited when S = 0
+ *   B*  = min(G_W, G_R, G_S)                                 (Eq. 1)
+ *   W*  = B* x W_B                                           (Eq. 2)
+ * A launch is illegal (W* = 0) when T outside [1, max_threads_per_block],
+ * R outside [0, max_vgprs_per_thread] or S outside [0, max_lds_per_block].
+ *
+ * Supported ranges (sa_arch_validate): wave_size in [2, 1024];
+ * max_threads_per_block in [1, 65536]; ceil(max_threads_per_block /
+ * wave_size) <= 64; max_waves_per_cu in [1, 64]; simd_per_cu in
+ * [1, max_waves_per_cu]; max_blocks_per_cu >= 1; vgpr_granule >= 1 with
+ * (ceil(max_vgprs_per_thread / vgpr_granule) + 1) x
+ * (ceil(max_threads_per_block / wave_size) + 1) <= 16384;
+ * vgprs_per_simd_lane in [1, 65536]; lds_per_cu in [1, 2^24]; lds_granule
+ * >= 1; max_lds_per_block in [0, 2^24]; n_cu in [1, 2048]; w_sat in
+ * [1, 4096]; max_unroll in [1, 64]; max_grid in [1, 2^18]; every cpi_*
+ * finite and >= 0.
+ */
+typedef struct sa_arch {
+  int32_t n_cu;                  /* compute units (mp)                         */
+  int32_t wave_size;             /* T_W                                        */
+  int32_t max_threads_per_block; /* T_B                                        */
+  int32_t max_waves_per_cu;      /* W_mp                                       */
+  int32_t max_blocks_per_cu;     /* B_mp                                       */
+  int32_t single_wave_exempt;    /* != 0: one-wave blocks not counted by B_mp  */
+  int32_t simd_per_cu;           /* register-file partitions per CU            */
+  int32_t vgprs_per_simd_lane;   /* registers per lane in one partition        */
+  int32_t vgpr_granule;          /* register allocation unit (per thread)      */
+  int32_t max_vgprs_per_thread;  /* R_T                                        */
+  int32_t lds_per_cu;            /* LDS pool per CU, bytes                     */
+  int32_t lds_granule;           /* LDS allocation unit, bytes                 */
+  int32_t max_lds_per_block;     /* S_B, bytes                                 */
+  int32_t w_sat;                 /* waves x unroll that hide latency           */
+  int32_t max_unroll;            /* largest legal unroll factor U              */
+  int32_t max_grid;              /* largest legal grid G (blocks)              */
+  float cpi_fp;                  /* c_f for floating-point ops                 */
+  float cpi_int;                 /* c_f for integer ops (FLOPS group)          */
+  float cpi_mem;                 /* c_m for loads + stores                     */
+  float cpi_ctrl;                /* c_b for branches                           */
+  float cpi_sync;                /* c_b for barriers, per wave of the block    */
+  float cpi_reg;                 /* c_r for register moves                     */
+} sa_arch;
+
+/*
+ * Per-variant instruction mix (Sec. III-B), structure of arrays of length
+ * n_variants, device pointers.  Counts are per thread.  A variant is valid
+ * when every count is in [0, 2^24), n_bar in [0, 2^14] and div in [0, 1]; an
+ * invalid variant makes all of its configurations illegal.
+ */
+typedef struct sa_variants {
+  const int32_t *n_fp;      /* floating-point ops                   -> O_fl   */
+  const int32_t *n_int;     /* integer ops                          -> O_fl   */
+  const int32_t *n_ld;      /* loads                                -> O_mem  */
+  const int32_t *n_st;      /* stores                               -> O_mem  */
+  const int32_t *n_br;      /* branches                             -> O_ctrl */
+  const int32_t *n_bar;     /* barriers                             -> O_ctrl */
+  const int32_t *n_reg;     /* register moves (NULL = all zero)     -> O_reg  */
+  const int32_t *lds_bytes; /* S: LDS bytes per block                         */
+  const float *div;         /* d: divergent fraction of the instruction stream */
+} sa_variants;
+
+/*
+ * Launch configurations, CSR by variant, device pointers.  `seg` has
+ * n_variants + 1 non-decreasing offsets with seg[0] = 0 and
+ * seg[n_variants] = n_evals; variant v owns evaluations [seg[v], seg[v+1]).
+ * A configuration is legal when 1 <= unroll <= max_unroll, 1 <= grid <=
+ * max_grid (when present) and its (block, regs, lds) launch is legal.
+ */
+typedef struct sa_configs {
+  const int64_t *seg;    /* n_variants + 1                                     */
+  const int32_t *block;  /* T: threads per block                              */
+  const int32_t *unroll; /* U: unroll factor                                  */
+  const int32_t *regs;   /* R: registers per thread                           */
+  const int32_t *grid;   /* G: blocks in the grid (NULL = no grid dimension)  */
+} sa_configs;
+
+/* Learned correction (declared for the corrected scoring mode). */
+typedef struct sa_mlp sa_mlp;
+
+/* Human-readable name of a status code (static storage). */
+const char *sa_status_string(sa_status status);
+
+/* Message describing the last error returned on the calling thread. */
+const char *sa_last_error(void);
+
+/* CDNA4 / MI355X constants without any device query (n_cu = 256): wave 64,
+ * 32 wave slots over 4 SIMDs, 512 unified VGPR/AGPR per SIMD lane (granule
+ * 8), 160 KiB LDS per CU (granule 512 B), 16 multi-wave blocks per CU,
+ * w_sat 32, U <= 64, G <= 2^18, CPI 2^-6 (fp, int), 2^-4 (memory, branch,
+ * barrier), 2^-5 (register moves).  Fills *out; SA_ERR_ARG if out is NULL. */
+sa_status sa_arch_gfx950(sa_arch *out);
+
+/* The same, with n_cu, wave size, thread and LDS limits read from HIP device
+ * `device` (hipGetDeviceProperties).  SA_ERR_NODEV without a device. */
+sa_status sa_arch_default_gfx950(int device, sa_arch *out);
+
+/* SA_OK when the descriptor is inside the supported ranges listed above. */
+sa_status sa_arch_validate(const sa_arch *arch);
+
+/* Bytes of workspace sa_score / sa_topk need for this problem size (an upper
+ * bound over every tile size the library may pick).  0 when k == 0.
+ * `flags` is reserved (pass 0). */
+size_t sa_workspace_bytes(int64_t n_variants, int64_t n_evals, int32_t k, int32_t flags);
+
+/*
+ * Occupancy only (Eqs. 1-5).  occ_waves[e] = W* of evaluation e (0 when
+ * illegal), int32[n_evals].  No workspace.
+ */
+sa_status sa_occupancy(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
+                       int64_t n_variants, int64_t n_evals, int32_t *occ_waves, void *stream);
+
+/*
+ * Occupancy, score and per-variant top-k in one pass over the batch.
+ *   score     float[n_evals] or NULL: predicted cost (+inf when illegal), the
+ *             binary32 sequence
+ *               P  = ((c_fp n_fp + c_int n_int) + c_mem (n_ld + n_st)) + c_reg n_reg
+ *               E  = (P + (c_ctrl n_br) / U) + c_sync (n_bar W_B)
+ *               E' = E (1 + d)
+ *               x  = W* U;  F = max(w_sat, x) / x              (no grid)
+ *                           F = (rounds cap max(w_sat, x)) / (G x),
+ *                               cap = n_cu B*, rounds = ceil(G / cap)
+ *               score = E' F
+ *             each step rounded to nearest even, no fused multiply-add.
+ *   occ_waves int32[n_evals] or NULL: W*.
+ *   topk_idx  int32[n_variants * k] or NULL: for variant v, row v holds the
+ *             local indices (0 .. seg[v+1]-seg[v]-1) of its k legal
+ *             configurations with the smallest (score, local index), in that
+ *             order; -1 past the number of legal configurations.
+ *   topk_val  float[n_variants * k] or NULL: the matching scores (+inf pad).
+ *   k         1 .. 64 when topk_idx or topk_val is given, else ignored.
+ *   mlp       must be NULL (plain static model).
+ *   workspace device buffer of sa_workspace_bytes(...) bytes (may be NULL
+ *             when no top-k is asked for).  Contents need no initialisation.
+ * Calls that share a workspace must be ordered on one stream.
+ */
+sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
+                   int64_t n_variants, int64_t n_evals, float *score, int32_t *occ_waves, int32_t k,
+                   int32_t *topk_idx, float *topk_val, const sa_mlp *mlp, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/*
+ * Segmented top-k over given keys: for each segment [seg[v], seg[v+1]) of
+ * keys (float[n_evals]) the k smallest finite-or-negative-infinite keys
+ * (NaN and +inf are excluded), ties by smaller local index; idx
+ * int32[n_variants * k] (-1 pad), val float[n_variants * k] or NULL (+inf
+ * pad).  Workspace as for sa_score.
+ */
+sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int64_t n_evals, int32_t k,
+                  int32_t *idx, float *val, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Tile size (evaluations per wave) the next calls on this thread use; 0
+ * restores the library's choice.  Must be a multiple of 256 in
+ * [1024, 65536].  Used by the tile autotuner. */
+sa_status sa_set_tile(int32_t evals_per_wave);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SA_H_ */

@@ -1,0 +1,295 @@
+"""Thin Python binding of the C ABI in ``include/sa.h`` (ctypes).
+
+Argument marshalling only: tensors are checked for device, dtype and
+contiguity and handed over as raw device pointers together with the current
+torch stream; every step of the model runs in the gfx950 kernels of
+``libsa.so``.  There is no CPU fallback: if the library is missing or no GPU
+is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsa.so")
+
+ARCH_INT_FIELDS = (
+    "n_cu", "wave_size", "max_threads_per_block", "max_waves_per_cu", "max_blocks_per_cu",
+    "single_wave_exempt", "simd_per_cu", "vgprs_per_simd_lane", "vgpr_granule",
+    "max_vgprs_per_thread", "lds_per_cu", "lds_granule", "max_lds_per_block", "w_sat",
+    "max_unroll", "max_grid",
+)
+ARCH_FLOAT_FIELDS = ("cpi_fp", "cpi_int", "cpi_mem", "cpi_ctrl", "cpi_sync", "cpi_reg")
+VARIANT_COLUMNS = ("n_fp", "n_int", "n_ld", "n_st", "n_br", "n_bar", "n_reg", "lds_bytes", "div")
+CONFIG_COLUMNS = ("seg", "block", "unroll", "regs", "grid")
+K_MAX = 64
+
+SA_OK = 0
+STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_ARG", -2: "SA_ERR_ALIGN", -3: "SA_ERR_NODEV", -4: "SA_ERR_WORKSPACE",
+                -5: "SA_ERR_HIP", -6: "SA_ERR_UNSUPPORTED"}
+
+# Every function the header declares (checked by the test suite).
+EXPORTED = (
+    "sa_status_string", "sa_last_error", "sa_arch_gfx950", "sa_arch_default_gfx950", "sa_arch_validate",
+    "sa_workspace_bytes", "sa_occupancy", "sa_score", "sa_topk", "sa_set_tile",
+)
+
+
+class SaArch(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ARCH_INT_FIELDS] + [(f, ctypes.c_float) for f in ARCH_FLOAT_FIELDS]
+
+
+class SaVariants(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in VARIANT_COLUMNS]
+
+
+class SaConfigs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in CONFIG_COLUMNS]
+
+
+class SAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load ``libsa.so`` (built by ``__graft_entry__.build()``)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("libsa.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            P, vp = ctypes.POINTER, ctypes.c_void_p
+            i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+            L.sa_status_string.argtypes = [i32]
+            L.sa_status_string.restype = ctypes.c_char_p
+            L.sa_last_error.argtypes = []
+            L.sa_last_error.restype = ctypes.c_char_p
+            L.sa_arch_gfx950.argtypes = [P(SaArch)]
+            L.sa_arch_gfx950.restype = i32
+            L.sa_arch_default_gfx950.argtypes = [ctypes.c_int, P(SaArch)]
+            L.sa_arch_default_gfx950.restype = i32
+            L.sa_arch_validate.argtypes = [P(SaArch)]
+            L.sa_arch_validate.restype = i32
+            L.sa_workspace_bytes.argtypes = [i64, i64, i32, i32]
+            L.sa_workspace_bytes.restype = sz
+            L.sa_occupancy.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp]
+            L.sa_occupancy.restype = i32
+            L.sa_score.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp, vp, vp,
+                                   sz, vp]
+            L.sa_score.restype = i32
+            L.sa_topk.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp, sz, vp]
+            L.sa_topk.restype = i32
+            L.sa_set_tile.argtypes = [i32]
+            L.sa_set_tile.restype = i32
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != SA_OK:
+        raise SAError(status, lib().sa_last_error().decode())
+
+
+def _arch_struct(arch: dict) -> SaArch:
+    s = SaArch()
+    for f in ARCH_INT_FIELDS:
+        setattr(s, f, int(arch[f]))
+    for f in ARCH_FLOAT_FIELDS:
+        setattr(s, f, float(arch[f]))
+    return s
+
+
+def _arch_dict(s: SaArch) -> dict:
+    d = {f: int(getattr(s, f)) for f in ARCH_INT_FIELDS}
+    d.update({f: float(getattr(s, f)) for f in ARCH_FLOAT_FIELDS})
+    return d
+
+
+def arch_gfx950() -> dict:
+    """CDNA4 / MI355X descriptor constants (no device query)."""
+    s = SaArch()
+    _check(lib().sa_arch_gfx950(ctypes.byref(s)))
+    return _arch_dict(s)
+
+
+def arch_default(device: int = 0) -> dict:
+    """CDNA4 descriptor with the limits HIP reports for `device`."""
+    s = SaArch()
+    _check(lib().sa_arch_default_gfx950(int(device), ctypes.byref(s)))
+    return _arch_dict(s)
+
+
+def arch_validate(arch: dict) -> None:
+    s = _arch_struct(arch)
+    _check(lib().sa_arch_validate(ctypes.byref(s)))
+
+
+def workspace_bytes(n_variants: int, n_evals: int, k: int) -> int:
+    return int(lib().sa_workspace_bytes(int(n_variants), int(n_evals), int(k), 0))
+
+
+def set_tile(evals_per_wave: int) -> None:
+    _check(lib().sa_set_tile(int(evals_per_wave)))
+
+
+# ------------------------------------------------------------------ tensors
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device (cuda) tensor, got %s" % (name, t.device))
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else ctypes.c_void_p(t.data_ptr() or None)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _variants_struct(v: dict) -> SaVariants:
+    torch = _torch()
+    s = SaVariants()
+    for f in VARIANT_COLUMNS:
+        key = f if f in v else ("lds" if f == "lds_bytes" else f)
+        t = v.get(key)
+        if t is None and f != "n_reg":
+            raise ValueError("variant column %s missing" % f)
+        setattr(s, f, _ptr(t, torch.float32 if f == "div" else torch.int32, f))
+    return s
+
+
+def _configs_struct(c: dict) -> SaConfigs:
+    torch = _torch()
+    s = SaConfigs()
+    for f in CONFIG_COLUMNS:
+        t = c.get(f)
+        if t is None and f != "grid":
+            raise ValueError("configuration column %s missing" % f)
+        setattr(s, f, _ptr(t, torch.int64 if f == "seg" else torch.int32, f))
+    return s
+
+
+def _sizes(variants: dict, configs: dict):
+    n_var = int(configs["seg"].numel()) - 1
+    n_evals = int(configs["block"].numel())
+    return n_var, n_evals
+
+
+def occupancy(arch: dict, variants: dict, configs: dict, out=None, stream=None):
+    """W* (active waves per CU, Eqs. 1-5) of every evaluation (int32)."""
+    torch = _torch()
+    n_var, n_evals = _sizes(variants, configs)
+    if out is None:
+        out = torch.empty(n_evals, dtype=torch.int32, device=configs["block"].device)
+    a = _arch_struct(arch)
+    _check(lib().sa_occupancy(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
+                              ctypes.byref(_configs_struct(configs)), n_var, n_evals,
+                              _ptr(out, torch.int32, "out"), _stream(stream)))
+    return out
+
+
+class Workspace:
+    """Device workspace for sa_score / sa_topk (256-byte aligned torch buffer)."""
+
+    def __init__(self, nbytes: int, device):
+        torch = _torch()
+        self.nbytes = int(nbytes)
+        self.buf = torch.empty(max(self.nbytes + 256, 256), dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.offset = (-base) % 256
+        self.ptr = ctypes.c_void_p(base + self.offset) if self.nbytes > 0 else None
+
+
+def score(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: bool = True,
+          want_occ: bool = True, want_topk: bool = True, outputs: dict | None = None,
+          workspace: Workspace | None = None, stream=None) -> dict:
+    """Occupancy, score and per-variant top-k in one pass (sa_score).
+
+    Returns a dict with ``occ`` (int32[n_evals]), ``score`` (float32[n_evals]),
+    ``idx`` (int32[n_var, k]) and ``val`` (float32[n_var, k]); entries not
+    requested are None.  `outputs` may supply preallocated tensors.
+    """
+    torch = _torch()
+    n_var, n_evals = _sizes(variants, configs)
+    dev = configs["seg"].device
+    o = dict(outputs or {})
+    if want_occ and o.get("occ") is None:
+        o["occ"] = torch.empty(n_evals, dtype=torch.int32, device=dev)
+    if want_score and o.get("score") is None:
+        o["score"] = torch.empty(n_evals, dtype=torch.float32, device=dev)
+    if want_topk:
+        if o.get("idx") is None:
+            o["idx"] = torch.empty((n_var, k), dtype=torch.int32, device=dev)
+        if o.get("val") is None:
+            o["val"] = torch.empty((n_var, k), dtype=torch.float32, device=dev)
+        if workspace is None:
+            workspace = Workspace(workspace_bytes(n_var, n_evals, k), dev)
+    for key in ("occ", "score", "idx", "val"):
+        o.setdefault(key, None)
+    a = _arch_struct(arch)
+    ws_ptr = workspace.ptr if (want_topk and workspace is not None) else None
+    ws_bytes = workspace.nbytes if (want_topk and workspace is not None) else 0
+    _check(lib().sa_score(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
+                          ctypes.byref(_configs_struct(configs)), n_var, n_evals,
+                          _ptr(o["score"] if want_score else None, torch.float32, "score"),
+                          _ptr(o["occ"] if want_occ else None, torch.int32, "occ"), int(k) if want_topk else 0,
+                          _ptr(o["idx"] if want_topk else None, torch.int32, "idx"),
+                          _ptr(o["val"] if want_topk else None, torch.float32, "val"), None,
+                          ws_ptr, ws_bytes, _stream(stream)))
+    return o
+
+
+def topk(keys, seg, k: int, *, workspace: Workspace | None = None, stream=None):
+    """Segmented top-k of float keys (sa_topk): (idx int32[n_var,k], val float32[n_var,k])."""
+    torch = _torch()
+    n_var = int(seg.numel()) - 1
+    n_evals = int(keys.numel())
+    idx = torch.empty((n_var, k), dtype=torch.int32, device=seg.device)
+    val = torch.empty((n_var, k), dtype=torch.float32, device=seg.device)
+    if workspace is None:
+        workspace = Workspace(workspace_bytes(n_var, n_evals, k), seg.device)
+    _check(lib().sa_topk(_ptr(keys, torch.float32, "keys"), _ptr(seg, torch.int64, "seg"), n_var, n_evals, int(k),
+                         _ptr(idx, torch.int32, "idx"), _ptr(val, torch.float32, "val"), workspace.ptr,
+                         workspace.nbytes, _stream(stream)))
+    return idx, val
+
+
+def device_batch(batch, device="cuda") -> tuple[dict, dict]:
+    """Copy a ``workloads.Batch`` to device tensors: (variants, configs)."""
+    torch = _torch()
+    var = {}
+    for f in ("n_fp", "n_int", "n_ld", "n_st", "n_br", "n_bar", "n_reg", "lds", "div"):
+        a = batch.variants[f]
+        var["lds_bytes" if f == "lds" else f] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    cfg = {"seg": torch.from_numpy(np.ascontiguousarray(batch.seg, dtype=np.int64)).to(device)}
+    for f in ("block", "unroll", "regs", "grid"):
+        a = getattr(batch, f)
+        cfg[f] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+    return var, cfg

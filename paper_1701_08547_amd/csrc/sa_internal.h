@@ -1,0 +1,68 @@
+// Internal interface between the C-ABI layer (sa_api.hip) and the gfx950
+// kernels (sa_eval.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sa.h"
+
+namespace sa {
+
+constexpr int kWaveSize = 64;           // gfx950 wavefront
+constexpr int kWavesPerBlock = 4;       // independent waves per workgroup
+constexpr int kBlockThreads = kWaveSize * kWavesPerBlock;
+constexpr int kItems = 4;               // rows of 64 evaluations in flight per wave
+constexpr int kCandCap = 256;           // candidate keys buffered per wave (LDS)
+constexpr int kTabBMax = 16384;         // occupancy table entries (bytes, dynamic LDS)
+constexpr int kMaxWB = 64;              // largest waves-per-block the tables hold
+constexpr int kMaxUnroll = 64;
+constexpr int32_t kTileMin = 1024;      // evaluations per wave-tile, smallest
+constexpr int32_t kTileMax = 65536;
+constexpr int32_t kTileDefault = 4096;
+
+// Descriptor as the kernels read it: the public fields plus the sizes and
+// division constants the host derives from them once per call.
+struct KArch {
+  int32_t n_cu, ws, max_threads, max_waves, max_blocks, exempt, simd, vgprs, vgpr_gran, max_vgprs;
+  int32_t lds_cu, lds_gran, max_lds, w_sat, max_unroll, max_grid;
+  float cfp, cint, cmem, cctrl, csync, creg;
+  int32_t nw;      // ceil(max_threads / ws): largest W_B
+  int32_t nr;      // ceil(max_vgprs / vgpr_gran): largest register granule count
+  uint32_t m_ws;   // floor(2^32 / ws) + 1   (exact floor division for n < 2^17)
+  uint32_t m_gran; // floor(2^32 / vgpr_gran) + 1, or 0 when vgpr_gran == 1
+};
+
+struct KVariants {
+  const int32_t *n_fp, *n_int, *n_ld, *n_st, *n_br, *n_bar, *n_reg, *lds;
+  const float *div;
+};
+
+struct KConfigs {
+  const int64_t *seg;
+  const int32_t *block, *unroll, *regs, *grid;
+};
+
+struct EvalLaunch {
+  KArch arch;
+  KVariants var;
+  KConfigs cfg;
+  const float *keys;      // sa_topk input (keys mode)
+  int64_t n_var, n_evals;
+  int32_t *occ;           // optional outputs
+  float *score;
+  int32_t *topk_idx;
+  float *topk_val;
+  uint64_t *frag;         // 2 slots of k keys per wave-tile
+  int32_t k;
+  int32_t tile;           // evaluations per wave-tile
+  int64_t n_tiles;
+  int32_t need_score;
+};
+
+enum class Mode { Model, Keys };
+
+hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream);
+hipError_t launch_merge(const EvalLaunch &L, hipStream_t stream);
+
+}  // namespace sa

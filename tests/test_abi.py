@@ -1,0 +1,150 @@
+"""The C-ABI library builds, loads and exports every entry point that
+include/sa.h declares; argument validation runs on the host before any HIP
+call, so these tests need no GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1701_08547_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "sa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sa_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(api.LIB_PATH):
+        from paper_1701_08547_amd import build
+
+        build.build()
+    return api.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    declared = _header_functions()
+    assert declared, "no declarations found"
+    assert sorted(api.EXPORTED) == declared
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    for code, name in api.STATUS_NAMES.items():
+        assert L.sa_status_string(code).decode() == name
+
+
+def test_gfx950_constants_equal_oracle_descriptor(L):
+    """The library and the oracle keep separate copies of the CDNA4
+    constants; they must agree field by field."""
+    lib_arch = api.arch_gfx950()
+    ora = oracle.arch_cdna4()
+    assert set(lib_arch) == set(ora)
+    for f in ora:
+        assert lib_arch[f] == ora[f], f
+    api.arch_validate(lib_arch)
+
+
+def test_paper_descriptors_are_supported(L):
+    for g in ("fermi", "kepler", "maxwell", "pascal"):
+        api.arch_validate(oracle.arch_paper(g))
+
+
+@pytest.mark.parametrize("field,value", [("n_cu", 0), ("wave_size", 1), ("max_waves_per_cu", 65),
+                                         ("max_unroll", 65), ("max_grid", 1 << 19), ("vgpr_granule", 0),
+                                         ("cpi_fp", float("nan")), ("cpi_mem", -1.0), ("simd_per_cu", 33),
+                                         ("max_threads_per_block", 65537)])
+def test_invalid_descriptor_rejected(L, field, value):
+    a = api.arch_gfx950()
+    a[field] = value
+    with pytest.raises(api.SAError) as e:
+        api.arch_validate(a)
+    assert e.value.status == -6
+
+
+def test_table_size_limit(L):
+    a = api.arch_gfx950()
+    a["vgpr_granule"] = 1
+    a["max_vgprs_per_thread"] = 1024  # 1025 x 17 > 16384 entries
+    with pytest.raises(api.SAError):
+        api.arch_validate(a)
+
+
+def test_workspace_bytes(L):
+    assert api.workspace_bytes(10, 0, 8) == 0
+    assert api.workspace_bytes(10, 100, 0) == 0
+    n = 16_384_000
+    assert api.workspace_bytes(1000, n, 8) >= 2 * (n // 1024) * 8 * 8
+
+
+def _null_args():
+    a = api._arch_struct(api.arch_gfx950())
+    v = api.SaVariants()
+    c = api.SaConfigs()
+    return a, v, c
+
+
+def test_argument_errors_before_any_launch(L):
+    a, v, c = _null_args()
+    by = ctypes.byref
+    # NULL arch
+    assert L.sa_score(None, by(v), by(c), 1, 1, None, None, 8, None, None, None, None, 0, None) == -1
+    # negative sizes
+    assert L.sa_score(by(a), by(v), by(c), -1, 1, None, None, 8, None, None, None, None, 0, None) == -1
+    # evaluations without variants
+    assert L.sa_occupancy(by(a), by(v), by(c), 0, 5, None, None) == -1
+    # NULL variant columns, then NULL seg
+    assert L.sa_occupancy(by(a), by(v), by(c), 1, 5, None, None) == -1
+    assert "variant" in L.sa_last_error().decode()
+    v_ok = api.SaVariants(*([8] * 9))
+    assert L.sa_occupancy(by(a), by(v_ok), by(c), 1, 5, None, None) == -1
+    assert "seg" in L.sa_last_error().decode()
+    # misaligned seg
+    c.seg = 4
+    assert L.sa_occupancy(by(a), by(v), by(c), 0, 0, None, None) == -2
+    # k outside [1, 64]
+    assert L.sa_topk(None, ctypes.c_void_p(8), 1, 0, 0, ctypes.c_void_p(16), None, None, 0, None) == -1
+    assert L.sa_topk(None, ctypes.c_void_p(8), 1, 0, 65, ctypes.c_void_p(16), None, None, 0, None) == -1
+    # workspace missing for a top-k over evaluations
+    assert L.sa_topk(ctypes.c_void_p(256), ctypes.c_void_p(8), 1, 100, 8, ctypes.c_void_p(16), None, None, 0,
+                     None) == -4
+    # workspace too small / misaligned
+    assert L.sa_topk(ctypes.c_void_p(256), ctypes.c_void_p(8), 1, 100, 8, ctypes.c_void_p(16), None,
+                     ctypes.c_void_p(256), 8, None) == -4
+    assert L.sa_topk(ctypes.c_void_p(256), ctypes.c_void_p(8), 1, 100, 8, ctypes.c_void_p(16), None,
+                     ctypes.c_void_p(128), 1 << 20, None) == -2
+    # the corrected mode is not reachable through sa_score in this build
+    v2 = api.SaVariants(*([8] * 9))
+    c2 = api.SaConfigs(8, 8, 8, 8, None)
+    assert L.sa_score(by(a), by(v2), by(c2), 1, 1, ctypes.c_void_p(8), None, 0, None, None, ctypes.c_void_p(8),
+                      None, 0, None) == -6
+
+
+def test_tile_setter(L):
+    with pytest.raises(api.SAError):
+        api.set_tile(1000)
+    with pytest.raises(api.SAError):
+        api.set_tile(512)
+    api.set_tile(2048)
+    api.set_tile(0)
+
+
+def test_no_device_is_reported(L):
+    try:
+        import torch
+
+        has_gpu = torch.cuda.device_count() > 0
+    except Exception:
+        has_gpu = False
+    if has_gpu:
+        pytest.skip("a GPU is present")
+    with pytest.raises(api.SAError) as e:
+        api.arch_default(0)
+    assert e.value.status == -3
