@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <initializer_list>
+
 #include "sa.h"
 #include "sa_internal.h"
 
@@ -26,6 +28,14 @@ sa_status fail(sa_status st, const char *fmt, ...) {
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int32_t log2_exact(int64_t x) {
+  int32_t s = 0;
+  while ((int64_t)1 << s < x) ++s;
+  return s;
+}
 
 sa_status check_arch(const sa_arch *a) {
   if (!a) return fail(SA_ERR_ARG, "arch is NULL");
@@ -50,6 +60,8 @@ sa_status check_arch(const sa_arch *a) {
   SA_RANGE(max_unroll, 1, sa::kMaxUnroll)
   SA_RANGE(max_grid, 1, 1 << 18)
 #undef SA_RANGE
+  if (!pow2(a->wave_size)) return fail(SA_ERR_UNSUPPORTED, "wave_size %d is not a power of two", a->wave_size);
+  if (!pow2(a->vgpr_granule)) return fail(SA_ERR_UNSUPPORTED, "vgpr_granule %d is not a power of two", a->vgpr_granule);
   const int64_t nw = ceil_div(a->max_threads_per_block, a->wave_size);
   const int64_t nr = ceil_div(a->max_vgprs_per_thread, a->vgpr_granule);
   if (nw > sa::kMaxWB) return fail(SA_ERR_UNSUPPORTED, "ceil(max_threads_per_block / wave_size) = %lld > %d", (long long)nw, sa::kMaxWB);
@@ -88,8 +100,8 @@ sa::KArch to_karch(const sa_arch *a) {
   k.creg = a->cpi_reg;
   k.nw = (int32_t)ceil_div(a->max_threads_per_block, a->wave_size);
   k.nr = (int32_t)ceil_div(a->max_vgprs_per_thread, a->vgpr_granule);
-  k.m_ws = (uint32_t)((1ull << 32) / (uint64_t)a->wave_size + 1ull);
-  k.m_gran = a->vgpr_granule == 1 ? 0u : (uint32_t)((1ull << 32) / (uint64_t)a->vgpr_granule + 1ull);
+  k.ws_shift = log2_exact(a->wave_size);
+  k.gran_shift = log2_exact(a->vgpr_granule);
   return k;
 }
 
@@ -97,6 +109,20 @@ int32_t pick_tile(int64_t n_evals) {
   if (g_tile > 0) return g_tile;
   (void)n_evals;
   return sa::kTileDefault;
+}
+
+// Dynamic LDS of the evaluation kernel: occupancy table, then the per-granule
+// wave counts, each rounded to 16 bytes.
+void set_lds_layout(sa::EvalLaunch &L) {
+  const int32_t tab = (L.arch.nr + 1) * (L.arch.nw + 1);
+  L.tab_wtot_off = (tab + 15) & ~15;
+  L.dyn_lds_bytes = L.tab_wtot_off + (((L.arch.nr + 1) + 15) & ~15);
+}
+
+bool all16(std::initializer_list<const void *> ps) {
+  for (const void *p : ps)
+    if (p && !aligned(p, 16)) return false;
+  return true;
 }
 
 size_t frag_bytes(int64_t n_evals, int32_t tile, int32_t k) {
@@ -247,6 +273,8 @@ sa_status sa_occupancy(const sa_arch *arch, const sa_variants *variants, const s
   L.n_tiles = ceil_div(n_evals, L.tile);
   L.need_score = 0;
   L.k = 0;
+  L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves}) ? 1 : 0;
+  set_lds_layout(L);
   hipError_t e = sa::launch_eval(L, sa::Mode::Model, configs->grid != nullptr, false, (hipStream_t)stream);
   return e == hipSuccess ? SA_OK : hip_fail(e, "sa_eval_kernel launch");
 }
@@ -282,6 +310,8 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   L.tile = pick_tile(n_evals);
   L.n_tiles = ceil_div(n_evals, L.tile);
   L.need_score = (score || topk) ? 1 : 0;
+  L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves, score}) ? 1 : 0;
+  set_lds_layout(L);
   if (topk) {
     const size_t need = frag_bytes(n_evals, L.tile, k);
     if (need > 0) {
@@ -324,6 +354,7 @@ sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int
   L.k = k;
   L.tile = pick_tile(n_evals);
   L.n_tiles = ceil_div(n_evals, L.tile);
+  L.vec = all16({keys}) ? 1 : 0;
   const size_t need = frag_bytes(n_evals, L.tile, k);
   if (need > 0) {
     if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);

@@ -6,18 +6,21 @@
 // Work decomposition.  The flattened evaluation space [0, n_evals) is cut
 // into wave-tiles of `tile` evaluations; each wave of a workgroup owns one
 // wave-tile and walks the variant segments that overlap it ("pieces").  Per
-// piece the variant's record is wave-uniform (scalar loads, computed once),
-// and the wave streams its evaluations in rows of 64 lanes, kItems rows in
-// flight, reading each structure-of-arrays column with coalesced dword loads.
+// piece the variant's record is wave-uniform and computed once.  The body of
+// a piece streams in chunks of 256 evaluations, each lane reading 4
+// consecutive evaluations of every structure-of-arrays column with one
+// 16-byte load, the next chunk's loads issued before the current chunk is
+// evaluated; unaligned heads and ragged tails go through a masked row path.
 //
 // Selection.  Keys are (order-preserving score bits << 32 | local index), a
 // total order.  Each wave keeps a threshold theta (the score of its current
 // k-th best) and appends only the evaluations at or below it to a per-wave
 // LDS candidate buffer (ballot + mbcnt compaction).  When the buffer fills,
-// the wave extracts the k smallest keys by k rounds of a wave-wide minimum
-// and tightens theta.  A piece that is a whole segment writes its result
-// directly; pieces of segments that span wave-tiles write k-key fragments
-// that sa_merge_kernel combines.
+// the wave extracts the k smallest keys: every lane sorts its share, then k
+// rounds take the wave-wide minimum of the lane heads with DPP row
+// reductions.  A piece that is a whole segment writes its result directly;
+// pieces of segments that span wave-tiles write k-key fragments that
+// sa_merge_kernel combines.
 //
 // Arithmetic.  Built with -ffp-contract=off and IEEE division, so every
 // binary32 step of the score rounds exactly once, in the documented order.
@@ -33,10 +36,38 @@ namespace {
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr uint32_t kThetaInit = 0xFF7FFFFFu;  // order key of FLT_MAX
 constexpr int32_t kUnlimited = 1 << 30;
+constexpr int kChunk = 64 * 4;                // evaluations per vector chunk
+#ifndef SA_PREFETCH
+#define SA_PREFETCH 1
+#endif
+#ifndef SA_NT_STORE
+#define SA_NT_STORE 1
+#endif
+#ifndef SA_WAVES_PER_EU
+#define SA_WAVES_PER_EU 4
+#endif
+constexpr int kPrefetch = SA_PREFETCH;        // chunks of loads in flight per wave
 
-// Order-preserving map of binary32 to uint32 (negative values flipped).
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+// Streaming 16-byte stores of the per-evaluation outputs.
+__device__ __forceinline__ void store4(int32_t *p, int32_t a, int32_t b, int32_t c, int32_t d) {
+  const v4i32 v = {a, b, c, d};
+  if (SA_NT_STORE) __builtin_nontemporal_store(v, (v4i32 *)p);
+  else *(v4i32 *)p = v;
+}
+__device__ __forceinline__ void store4(float *p, float a, float b, float c, float d) {
+  const v4f32 v = {a, b, c, d};
+  if (SA_NT_STORE) __builtin_nontemporal_store(v, (v4f32 *)p);
+  else *(v4f32 *)p = v;
+}
+
+// Order-preserving map of binary32 to uint32 (negative values flipped, -0
+// ordered as +0 so equal values tie and fall back to the index).
 __device__ __forceinline__ uint32_t order_key(float f) {
   uint32_t b = __float_as_uint(f);
+  b = (b == 0x80000000u) ? 0u : b;
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 __device__ __forceinline__ float order_key_inv(uint32_t k) {
@@ -55,7 +86,6 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
   uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ int32_t uniform32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Orders this wave's LDS accesses before/after (LDS ops of one wave complete
 // in order; this keeps the compiler from moving them across).
@@ -65,22 +95,26 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
-  int lo = __shfl_xor((int)(uint32_t)v, mask, 64);
-  int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+// Minimum over the 64 lanes: four DPP steps leave every lane of a 16-lane row
+// holding the row minimum, then the four row minima are combined.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min(uint32_t v) {
+  uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+  return o < v ? o : v;
 }
-
-__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    uint64_t o = shfl_xor64(v, m);
-    v = o < v ? o : v;
-  }
-  return v;
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = dpp_min<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_min<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_min<0x141>(v);  // row_half_mirror
+  v = dpp_min<0x140>(v);  // row_mirror
+  uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+  uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+  uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+  uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+  a = a < b ? a : b;
+  c = c < d ? c : d;
+  return a < c ? a : c;
 }
-
-__device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 // Clamp a segment offset into [0, n]: keeps every access in bounds even when
 // the offsets are not a valid CSR.
@@ -109,7 +143,7 @@ __device__ int64_t find_segment(const int64_t *seg, int64_t n_var, int64_t n_eva
 // correction step each way makes it exact.
 __device__ __forceinline__ int32_t udiv_rcp(int32_t a, int32_t b, float rcp) {
   int32_t q = (int32_t)((float)a * rcp);
-  int32_t r = a - q * b;
+  int32_t r = a - (int32_t)__umul24((uint32_t)q, (uint32_t)b);
   q = (r < 0) ? q - 1 : q;
   r = (r < 0) ? r + b : r;
   q = (r >= b) ? q + 1 : q;
@@ -124,108 +158,378 @@ struct Selector {
   uint32_t theta;  // order key of the current k-th best score (uniform)
 };
 
+__device__ __forceinline__ void cas64(uint64_t &a, uint64_t &b) {
+  uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
 // Reduce buf[0, count) to its k smallest keys: afterwards lane r < found holds
 // the r-th smallest (kKeyNone elsewhere), buf[0, found) holds them too and
-// theta is the k-th smallest score when k keys exist.
+// theta is the k-th smallest score when k keys exist.  Each lane sorts its
+// eight keys (Batcher's odd-even merge network); each of the k rounds takes
+// the minimum of the lane heads and the owner pops its head.
 __device__ uint64_t select_k(Selector &s, int k, int lane) {
+  static_assert(kCandCap == 8 * 64, "select_k holds eight keys per lane");
   wave_lds_sync();
-  constexpr int J = kCandCap / 64;
-  uint64_t r[J];
+  const uint32_t i0 = 8u * (uint32_t)lane;
+  uint64_t r[8];
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    uint32_t i = (uint32_t)lane + 64u * j;
-    r[j] = i < s.count ? s.buf[i] : kKeyNone;
-  }
+  for (int j = 0; j < 8; ++j) r[j] = i0 + j < s.count ? s.buf[i0 + j] : kKeyNone;
+  cas64(r[0], r[1]); cas64(r[2], r[3]); cas64(r[4], r[5]); cas64(r[6], r[7]);
+  cas64(r[0], r[2]); cas64(r[1], r[3]); cas64(r[4], r[6]); cas64(r[5], r[7]);
+  cas64(r[1], r[2]); cas64(r[5], r[6]);
+  cas64(r[0], r[4]); cas64(r[1], r[5]); cas64(r[2], r[6]); cas64(r[3], r[7]);
+  cas64(r[2], r[4]); cas64(r[3], r[5]);
+  cas64(r[1], r[2]); cas64(r[3], r[4]); cas64(r[5], r[6]);
   uint64_t mine = kKeyNone;
   int found = 0;
+  uint32_t last_hi = 0;
   for (int q = 0; q < k; ++q) {
-    uint64_t m = r[0];
+    const uint32_t hi = (uint32_t)(r[0] >> 32), lo = (uint32_t)r[0];
+    const uint32_t mh = wave_min_u32(hi);
+    if (mh == 0xFFFFFFFFu) break;
+    const uint64_t tie = __ballot(hi == mh);
+    int owner;
+    uint32_t ml;
+    if (__popcll(tie) == 1) {
+      owner = __ffsll((long long)tie) - 1;
+      ml = (uint32_t)__builtin_amdgcn_readlane((int)lo, owner);
+    } else {
+      ml = wave_min_u32(hi == mh ? lo : 0xFFFFFFFFu);
+      owner = __ffsll((long long)__ballot(hi == mh && lo == ml)) - 1;
+    }
+    if (lane == q) mine = ((uint64_t)mh << 32) | ml;
+    if (lane == owner) {
 #pragma unroll
-    for (int j = 1; j < J; ++j) m = min64(m, r[j]);
-    m = wave_min64(m);
-    if (m == kKeyNone) break;
-    if (lane == q) mine = m;
-#pragma unroll
-    for (int j = 0; j < J; ++j) r[j] = (r[j] == m) ? kKeyNone : r[j];
+      for (int j = 0; j < 7; ++j) r[j] = r[j + 1];
+      r[7] = kKeyNone;
+    }
+    last_hi = mh;
     ++found;
   }
   wave_lds_sync();
   if (lane < found) s.buf[lane] = mine;
   s.count = (uint32_t)found;
-  if (found == k) {
-    uint32_t hi = (uint32_t)(mine >> 32);
-    s.theta = (uint32_t)__builtin_amdgcn_readlane((int)hi, k - 1);
-  }
+  if (found == k) s.theta = last_hi;
   wave_lds_sync();
   return mine;
 }
 
-// Offer one row of 64 keys (one per lane, `cand` marks the lanes to offer).
-__device__ __forceinline__ void offer(Selector &s, bool cand, uint64_t key, int k, int lane) {
-  uint64_t bal = __ballot(cand);
-  if (bal == 0) return;
-  uint32_t c = (uint32_t)__popcll(bal);
-  if (s.count + c > (uint32_t)kCandCap) select_k(s, k, lane);
-  uint32_t pos = s.count + mbcnt64(bal);
-  if (cand) s.buf[pos] = key;
-  s.count += c;
+// Flush the buffer when fewer than `need` slots are free.  Called before a
+// batch is evaluated, where few registers are live.
+__device__ __forceinline__ void make_room(Selector &s, uint32_t need, int k, int lane) {
+  if (s.count + need > (uint32_t)kCandCap) select_k(s, k, lane);
 }
 
-__device__ __forceinline__ void write_final(uint64_t mine, int k, int lane, int64_t v, int32_t *idx, float *val) {
+// Offer N rows of 64 keys (`cand[i]` marks the lanes offering key[i]) by
+// ballot + mbcnt compaction; make_room(64 N) must have run first.
+template <int N>
+__device__ __forceinline__ void offer(Selector &s, const bool (&cand)[N], const uint64_t (&key)[N]) {
+  static_assert(N * 64 + SA_K_MAX <= kCandCap, "buffer must hold k keys plus one batch");
+  uint64_t bal[N];
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    bal[i] = __ballot(cand[i]);
+    c += (uint32_t)__popcll(bal[i]);
+  }
+  if (c == 0) return;
+  uint32_t pos = s.count;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (cand[i]) s.buf[pos + mbcnt64(bal[i])] = key[i];
+    pos += (uint32_t)__popcll(bal[i]);
+  }
+  s.count = pos;
+}
+
+// Final row of variant v.  Values come from the key, or (keys mode) from the
+// caller's array so that the sign of a zero key survives.
+__device__ __forceinline__ void write_final(uint64_t mine, int k, int lane, int64_t v, int32_t *idx, float *val,
+                                            const float *keys, int64_t s0) {
   if (lane < k) {
-    bool none = (mine == kKeyNone);
-    if (idx) idx[v * k + lane] = none ? -1 : (int32_t)(uint32_t)mine;
-    if (val) val[v * k + lane] = none ? __builtin_huge_valf() : order_key_inv((uint32_t)(mine >> 32));
+    const bool none = (mine == kKeyNone);
+    const int32_t li = (int32_t)(uint32_t)mine;
+    if (idx) idx[v * k + lane] = none ? -1 : li;
+    if (val) {
+      float x = __builtin_huge_valf();
+      if (!none) x = keys ? keys[s0 + li] : order_key_inv((uint32_t)(mine >> 32));
+      val[v * k + lane] = x;
+    }
   }
 }
 
-// ---------------------------------------------------------------- main kernel
+// ---------------------------------------------------------------- evaluation
 
 struct __align__(16) WaveLds {
-  float a4[kMaxUnroll];        // (c_ctrl n_br) / U for U = 1 .. max_unroll
-  float a5[kMaxWB + 1];        // c_sync (n_bar W_B)    for W_B = 1 .. nw
+  float a4[kMaxUnroll];  // (c_ctrl n_br) / U for U = 1 .. max_unroll
+  float a5[kMaxWB + 1];  // c_sync (n_bar W_B)    for W_B = 1 .. nw
   uint64_t cand[kCandCap];
 };
 
+// Wave-uniform state of the piece being evaluated.
+struct Piece {
+  bool valid;      // variant counts in range
+  int32_t gs;      // Eq. 5 bound for the variant's LDS
+  float P, D;      // Eq. 6 per-variant sum, divergence weight 1 + d
+  int64_t s0;      // segment start (local index origin)
+  const float *a4, *a5;
+};
+
+struct Tables {
+  const uint8_t *tab_b;  // [rg][W_B] -> min(G_W, G_R)
+  const float *rcap;     // [B] -> 1 / (n_cu B)
+};
+
+// One configuration: W* (0 if illegal) and the binary32 score (+inf if
+// illegal or not asked for).  Products of small non-negative integers use
+// the full-rate 24-bit multiplier (every operand here is below 2^24).
+template <bool HAS_GRID>
+__device__ __forceinline__ void eval_cfg(const KArch &A, const Tables &tb, const Piece &pc, int32_t T, int32_t U,
+                                         int32_t R, int32_t G, bool in, bool need_score, int32_t &W, float &sc) {
+  // bitwise '&' keeps the legality test free of branches
+  bool ok = in & pc.valid & ((uint32_t)(T - 1) < (uint32_t)A.max_threads) &
+            ((uint32_t)(U - 1) < (uint32_t)A.max_unroll) & ((uint32_t)R <= (uint32_t)A.max_vgprs);
+  if (HAS_GRID) ok = ok & ((uint32_t)(G - 1) < (uint32_t)A.max_grid);
+  // only the table indices need sanitising; G of an illegal lane is discarded
+  T = ok ? T : 1;
+  U = ok ? U : 1;
+  R = ok ? R : 0;
+  // Eqs. 1-5: waves per block, register granules, bound table, LDS bound
+  const int32_t WB = (T + A.ws - 1) >> A.ws_shift;
+  const int32_t rg = (R + (1 << A.gran_shift) - 1) >> A.gran_shift;
+  int32_t B = tb.tab_b[__umul24(rg, A.nw + 1) + WB];
+  B = B < pc.gs ? B : pc.gs;
+  B = ok ? B : 0;
+  W = __umul24(B, WB);
+  sc = __builtin_huge_valf();
+  if (need_score) {
+    // Eq. 6 per-configuration part, fixed binary32 order
+    float E = pc.P + pc.a4[U - 1];
+    E = E + pc.a5[WB];
+    const float Ed = E * pc.D;
+    const int32_t x = __umul24(W, U);
+    const int32_t hide = x > A.w_sat ? x : A.w_sat;
+    int32_t num, den;
+    if (HAS_GRID) {
+      const int32_t cap = __umul24(A.n_cu, B);
+      const int32_t rounds = udiv_rcp(G + cap - 1, cap, tb.rcap[B]);
+      num = __umul24(__umul24(rounds, cap), hide);
+      den = __umul24(G, x);
+    } else {
+      num = hide;
+      den = x;
+    }
+    const float F = (float)num / (float)den;
+    sc = (B > 0) ? Ed * F : __builtin_huge_valf();
+  }
+}
+
 template <Mode MODE, bool HAS_GRID, bool TOPK>
-__global__ __launch_bounds__(kBlockThreads) void sa_eval_kernel(EvalLaunch L) {
-  // Per-workgroup tables: occupancy bound by (register granules, W_B) and
-  // 1/(n_cu B*) for the grid-round division.
-  extern __shared__ __align__(16) uint8_t tab_b[];  // (nr + 1) x (nw + 1) bytes, dynamic
+struct Evaluator {
+  const EvalLaunch &L;
+  const Tables &tb;
+  const Piece &pc;
+  Selector &sel;
+  int lane;
+
+  // Masked rows over [base, end): lane l takes base + 64 i + l.  end - base <= 256.
+  __device__ __forceinline__ void masked(int64_t base, int64_t end) {
+    if constexpr (TOPK) make_room(sel, kChunk, L.k, lane);
+    const int rem = (int)(end - base);
+    int32_t Tv[4], Uv[4], Rv[4], Gv[4];
+    float Kv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = lane + 64 * i;
+      const bool in = j < rem;
+      if constexpr (MODE == Mode::Model) {
+        Tv[i] = in ? L.cfg.block[base + j] : 0;
+        Uv[i] = in ? L.cfg.unroll[base + j] : 0;
+        Rv[i] = in ? L.cfg.regs[base + j] : 0;
+        Gv[i] = (HAS_GRID && in) ? L.cfg.grid[base + j] : 1;
+      } else {
+        Kv[i] = in ? L.keys[base + j] : __builtin_huge_valf();
+      }
+    }
+    bool cand[4];
+    uint64_t key[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = lane + 64 * i;
+      const bool in = j < rem;
+      const int64_t e = base + j;
+      float sc;
+      bool ok;
+      if constexpr (MODE == Mode::Model) {
+        int32_t W;
+        eval_cfg<HAS_GRID>(L.arch, tb, pc, Tv[i], Uv[i], Rv[i], Gv[i], in, L.need_score, W, sc);
+        if (L.occ && in) L.occ[e] = W;
+        if (L.score && in) L.score[e] = sc;
+        ok = W > 0;
+      } else {
+        sc = Kv[i];
+        ok = in && sc < __builtin_huge_valf();
+      }
+      const uint32_t kk = order_key(sc);
+      cand[i] = ok && kk <= sel.theta;
+      key[i] = ((uint64_t)kk << 32) | (uint32_t)(e - pc.s0);
+    }
+    if constexpr (TOPK) offer<4>(sel, cand, key);
+  }
+
+  struct Cols {
+    int4 T, U, R, G;
+    float4 K;
+  };
+
+  __device__ __forceinline__ Cols load_chunk(int64_t base) const {
+    Cols c;
+    const int64_t o = base + 4 * lane;
+    if constexpr (MODE == Mode::Model) {
+      c.T = *(const int4 *)(L.cfg.block + o);
+      c.U = *(const int4 *)(L.cfg.unroll + o);
+      c.R = *(const int4 *)(L.cfg.regs + o);
+      if (HAS_GRID) c.G = *(const int4 *)(L.cfg.grid + o);
+      else c.G = make_int4(1, 1, 1, 1);
+    } else {
+      c.K = *(const float4 *)(L.keys + o);
+    }
+    return c;
+  }
+
+  __device__ __forceinline__ void chunk(const Cols &c, int64_t base) {
+    const int64_t o = base + 4 * lane;
+    float sc[4];
+    int32_t W[4];
+    bool ok[4];
+    if constexpr (MODE == Mode::Model) {
+      const int32_t Ts[4] = {c.T.x, c.T.y, c.T.z, c.T.w};
+      const int32_t Us[4] = {c.U.x, c.U.y, c.U.z, c.U.w};
+      const int32_t Rs[4] = {c.R.x, c.R.y, c.R.z, c.R.w};
+      const int32_t Gs[4] = {c.G.x, c.G.y, c.G.z, c.G.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        eval_cfg<HAS_GRID>(L.arch, tb, pc, Ts[i], Us[i], Rs[i], Gs[i], true, L.need_score, W[i], sc[i]);
+        ok[i] = W[i] > 0;
+      }
+      if (L.occ) store4(L.occ + o, W[0], W[1], W[2], W[3]);
+      if (L.score) store4(L.score + o, sc[0], sc[1], sc[2], sc[3]);
+    } else {
+      sc[0] = c.K.x;
+      sc[1] = c.K.y;
+      sc[2] = c.K.z;
+      sc[3] = c.K.w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ok[i] = sc[i] < __builtin_huge_valf();
+    }
+    if constexpr (TOPK) {
+      const uint32_t li = (uint32_t)(o - pc.s0);
+      bool cand[4];
+      uint64_t key[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // model scores are +0 .. +inf: the key is the bit pattern with the
+        // sign bit set, and +inf's key lies above every threshold
+        const uint32_t kk = MODE == Mode::Model ? (__float_as_uint(sc[i]) | 0x80000000u) : order_key(sc[i]);
+        cand[i] = MODE == Mode::Model ? kk <= sel.theta : (ok[i] && kk <= sel.theta);
+        key[i] = ((uint64_t)kk << 32) | (li + (uint32_t)i);
+      }
+      offer<4>(sel, cand, key);
+    }
+  }
+
+  // [e, pe): unaligned head and ragged tail masked, aligned body vectorised
+  // with the next chunk's loads in flight while the current one is evaluated.
+  __device__ void run(int64_t e, int64_t pe) {
+    int64_t body = e;
+    if (L.vec) {
+      int64_t a0 = (e + 3) & ~(int64_t)3;
+      a0 = a0 < pe ? a0 : pe;
+      if (a0 > e) masked(e, a0);
+      body = a0;
+      const int64_t nfull = (pe - a0) / kChunk;
+      if (nfull > 0) {
+        // kPrefetch chunks in flight: q[0] is evaluated while q[1..] and the
+        // newly issued chunk are still loading
+        Cols q[kPrefetch];
+#pragma unroll
+        for (int d = 0; d < kPrefetch; ++d)
+          if (d < nfull) q[d] = load_chunk(a0 + d * kChunk);
+        for (int64_t it = 0; it < nfull; ++it) {
+          const int64_t base = a0 + it * kChunk;
+          if constexpr (TOPK) make_room(sel, kChunk, L.k, lane);
+          // the prefetch is unconditional (a conditional load would make the
+          // compiler wait for every load before evaluating q[0]); past the
+          // last chunk it re-reads the current one, which is still cached
+          const bool more = it + kPrefetch < nfull;
+          const Cols nxt = load_chunk(more ? base + kPrefetch * kChunk : base);
+          chunk(q[0], base);
+#pragma unroll
+          for (int d = 0; d + 1 < kPrefetch; ++d) q[d] = q[d + 1];
+          q[kPrefetch - 1] = nxt;
+        }
+        body = a0 + nfull * kChunk;
+      }
+    }
+    for (int64_t base = body; base < pe; base += kChunk) masked(base, (pe - base) < kChunk ? pe : base + kChunk);
+  }
+};
+
+template <Mode MODE, bool HAS_GRID, bool TOPK>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SA_WAVES_PER_EU)))
+void sa_eval_kernel(EvalLaunch L) {
+  // Dynamic LDS: the occupancy table [rg][W_B] followed by waves-by-registers
+  // per register-granule count.
+  extern __shared__ __align__(16) uint8_t dyn_lds[];
   __shared__ float tab_rcap[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 1];
+  __shared__ uint8_t tab_blim[kMaxWB + 1];
   __shared__ WaveLds wl[kWavesPerBlock];
 
   const KArch &A = L.arch;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = tid / kWaveSize;
+  const int row = A.nw + 1;
+  uint8_t *tab_b = dyn_lds;
+  uint8_t *tab_wtot = dyn_lds + L.tab_wtot_off;
 
   if constexpr (MODE == Mode::Model) {
-    const int row = A.nw + 1;
+    // waves the register file admits per register-granule count (Eq. 4 plain
+    // reading), all slots when no registers are named
+    const int slots = A.max_waves / A.simd;
+    for (int rg = tid; rg <= A.nr; rg += kBlockThreads) {
+      int wtot = A.max_waves;
+      if (rg > 0) {
+        const int per_simd = A.vgprs / (rg * A.vgpr_gran);
+        wtot = A.simd * (per_simd < slots ? per_simd : slots);
+      }
+      tab_wtot[rg] = (uint8_t)wtot;
+    }
+    // Eq. 3 block slots, and ceil(2^16 / W_B) for exact small divisions
+    for (int wb = tid; wb <= A.nw; wb += kBlockThreads) {
+      tab_mwb[wb] = wb > 0 ? (65536u + (uint32_t)wb - 1u) / (uint32_t)wb : 0u;
+      const int blim = (wb == 1 && A.exempt) ? 255 : (A.max_blocks < 255 ? A.max_blocks : 255);
+      tab_blim[wb] = (uint8_t)blim;
+    }
+    for (int i = tid; i <= A.max_waves; i += kBlockThreads) tab_rcap[i] = i > 0 ? 1.0f / (float)(A.n_cu * i) : 0.0f;
+    __syncthreads();
+    // min(G_W, G_R) = min(B_lim, floor(wtot / W_B)): the register bound never
+    // exceeds floor(max_waves / W_B), the wave-slot part of Eq. 3
     const int n_tab = (A.nr + 1) * row;
     for (int i = tid; i < n_tab; i += kBlockThreads) {
-      int rg = i / row, wb = i - rg * row;
-      int b = 0;
+      const int rg = i / row, wb = i - rg * row;
+      uint32_t b = 0;
       if (wb >= 1) {
-        // waves the register file admits (Eq. 4 plain reading), all when R = 0
-        int wtot = A.max_waves;
-        if (rg > 0) {
-          int per_simd = A.vgprs / (rg * A.vgpr_gran);
-          int slots = A.max_waves / A.simd;
-          wtot = A.simd * (per_simd < slots ? per_simd : slots);
-        }
-        // Eq. 3 wave slots and block slots (min over both); registers bound
-        // floor(wtot / W_B) never exceeds floor(max_waves / W_B).
-        int by_regs = wtot / wb;
-        int by_slots = (wb == 1 && A.exempt) ? kUnlimited : A.max_blocks;
-        b = by_regs < by_slots ? by_regs : by_slots;
+        b = ((uint32_t)tab_wtot[rg] * tab_mwb[wb]) >> 16;
+        b = b < tab_blim[wb] ? b : tab_blim[wb];
       }
       tab_b[i] = (uint8_t)b;
     }
-    for (int i = tid; i <= A.max_waves; i += kBlockThreads)
-      tab_rcap[i] = i > 0 ? 1.0f / (float)(A.n_cu * i) : 0.0f;
   }
-  __syncthreads();  // the only workgroup barrier: waves are independent below
+  __syncthreads();  // waves are independent below
 
   const int64_t wt = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (wt >= L.n_tiles) return;
@@ -237,20 +541,27 @@ __global__ __launch_bounds__(kBlockThreads) void sa_eval_kernel(EvalLaunch L) {
 
   Selector sel;
   sel.buf = wl[w].cand;
+  sel.count = 0;
+  sel.theta = kThetaInit;
+  const Tables tb{tab_b, tab_rcap};
 
   int64_t v = find_segment(seg, L.n_var, n_evals, t0, lane);
   int64_t e = t0;
   for (; v < L.n_var && e < t1; ++v) {
-    const int64_t s0 = clamp_off(seg[v], n_evals);
-    const int64_t s1 = clamp_off(seg[v + 1], n_evals);
+    const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
+    const int64_t s1 = uniform64(clamp_off(seg[v + 1], n_evals));
     int64_t pe = s1 > e ? s1 : e;
     pe = pe < t1 ? pe : t1;
     if (pe <= e) continue;
 
-    // ---- per-variant record (wave-uniform)
-    bool valid = true;
-    int32_t gs = 0;
-    float P = 0.f, D = 1.f;
+    Piece pc;
+    pc.valid = true;
+    pc.gs = 0;
+    pc.P = 0.f;
+    pc.D = 1.f;
+    pc.s0 = s0;
+    pc.a4 = wl[w].a4;
+    pc.a5 = wl[w].a5;
     if constexpr (MODE == Mode::Model) {
       const int32_t nfp = L.var.n_fp[v], nint = L.var.n_int[v], nld = L.var.n_ld[v], nst = L.var.n_st[v];
       const int32_t nbr = L.var.n_br[v], nbar = L.var.n_bar[v];
@@ -258,29 +569,30 @@ __global__ __launch_bounds__(kBlockThreads) void sa_eval_kernel(EvalLaunch L) {
       const int32_t S = L.var.lds[v];
       const float d = L.var.div[v];
       const uint32_t cmax = 1u << 24;
-      valid = (uint32_t)nfp < cmax && (uint32_t)nint < cmax && (uint32_t)nld < cmax && (uint32_t)nst < cmax &&
-              (uint32_t)nbr < cmax && (uint32_t)nreg < cmax && (uint32_t)nbar <= (1u << 14) && d >= 0.0f &&
-              d <= 1.0f;
+      pc.valid = (uint32_t)nfp < cmax && (uint32_t)nint < cmax && (uint32_t)nld < cmax && (uint32_t)nst < cmax &&
+                 (uint32_t)nbr < cmax && (uint32_t)nreg < cmax && (uint32_t)nbar <= (1u << 14) && d >= 0.0f &&
+                 d <= 1.0f;
       // Eq. 5 with a floor; S = 0 does not limit
       if (S == 0) {
-        gs = kUnlimited;
+        pc.gs = kUnlimited;
       } else if (S < 0 || S > A.max_lds) {
-        gs = 0;
+        pc.gs = 0;
       } else {
-        int32_t alloc = ((S + A.lds_gran - 1) / A.lds_gran) * A.lds_gran;
-        gs = A.lds_cu / alloc;
+        const int32_t alloc = ((S + A.lds_gran - 1) / A.lds_gran) * A.lds_gran;
+        pc.gs = A.lds_cu / alloc;
       }
       // Eq. 6 per-variant part, fixed binary32 order
-      float s1f = A.cfp * (float)nfp;
-      float s2f = A.cint * (float)nint;
-      float s3f = A.cmem * (float)(nld + nst);
-      float s6f = A.creg * (float)nreg;
-      P = s1f + s2f;
+      const float s1f = A.cfp * (float)nfp;
+      const float s2f = A.cint * (float)nint;
+      const float s3f = A.cmem * (float)(nld + nst);
+      const float s6f = A.creg * (float)nreg;
+      float P = s1f + s2f;
       P = P + s3f;
       P = P + s6f;
+      pc.P = P;
       const float A4 = A.cctrl * (float)nbr;
-      D = 1.0f + d;
-      // per-wave tables for this variant
+      pc.D = 1.0f + d;
+      // per-wave tables of the variant: branch term per U, barrier term per W_B
       wave_lds_sync();
       if (lane < A.max_unroll) wl[w].a4[lane] = A4 / (float)(lane + 1);
       if (lane < A.nw) wl[w].a5[lane + 1] = A.csync * (float)(nbar * (lane + 1));
@@ -291,99 +603,13 @@ __global__ __launch_bounds__(kBlockThreads) void sa_eval_kernel(EvalLaunch L) {
       sel.count = 0;
       sel.theta = kThetaInit;
     }
-
-    for (int64_t base = e; base < pe; base += 64 * kItems) {
-      const int64_t rem64 = pe - base;
-      const int rem = rem64 < 64 * kItems ? (int)rem64 : 64 * kItems;
-      int32_t Tv[kItems], Uv[kItems], Rv[kItems], Gv[kItems];
-      float Kv[kItems];
-      if constexpr (MODE == Mode::Model) {
-        const int32_t *pT = L.cfg.block + base;
-        const int32_t *pU = L.cfg.unroll + base;
-        const int32_t *pR = L.cfg.regs + base;
-        const int32_t *pG = HAS_GRID ? L.cfg.grid + base : nullptr;
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-          const int j = lane + 64 * i;
-          const bool in = j < rem;
-          Tv[i] = in ? pT[j] : 0;
-          Uv[i] = in ? pU[j] : 0;
-          Rv[i] = in ? pR[j] : 0;
-          Gv[i] = (HAS_GRID && in) ? pG[j] : 1;
-        }
-      } else {
-        const float *pK = L.keys + base;
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-          const int j = lane + 64 * i;
-          Kv[i] = j < rem ? pK[j] : __builtin_huge_valf();
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < kItems; ++i) {
-        const int j = lane + 64 * i;
-        const bool in = j < rem;
-        const int64_t eidx = base + j;
-        float sc = __builtin_huge_valf();
-        bool ok;
-        if constexpr (MODE == Mode::Model) {
-          int32_t T = Tv[i], U = Uv[i], R = Rv[i], G = Gv[i];
-          ok = in && valid && (uint32_t)(T - 1) < (uint32_t)A.max_threads &&
-               (uint32_t)(U - 1) < (uint32_t)A.max_unroll && (uint32_t)R <= (uint32_t)A.max_vgprs;
-          if (HAS_GRID) ok = ok && (uint32_t)(G - 1) < (uint32_t)A.max_grid;
-          T = ok ? T : 1;
-          U = ok ? U : 1;
-          R = ok ? R : 0;
-          G = ok ? G : 1;
-          // Eqs. 1-5: W_B, register granules, bound table, LDS bound
-          const int32_t WB = (int32_t)__umulhi((uint32_t)(T + A.ws - 1), A.m_ws);
-          const int32_t rg = A.m_gran ? (int32_t)__umulhi((uint32_t)(R + A.vgpr_gran - 1), A.m_gran) : R;
-          int32_t B = tab_b[rg * (A.nw + 1) + WB];
-          B = B < gs ? B : gs;
-          B = ok ? B : 0;
-          const int32_t W = B * WB;
-          if (L.occ && in) L.occ[eidx] = W;
-          if (L.need_score) {
-            const int32_t Bs = B > 0 ? B : 1;
-            const float a4 = wl[w].a4[U - 1];
-            const float a5 = wl[w].a5[WB];
-            float E = P + a4;
-            E = E + a5;
-            const float Ed = E * D;
-            const int32_t x = Bs * WB * U;
-            const int32_t hide = x > A.w_sat ? x : A.w_sat;
-            int32_t num, den;
-            if (HAS_GRID) {
-              const int32_t cap = A.n_cu * Bs;
-              const int32_t rounds = udiv_rcp(G + cap - 1, cap, tab_rcap[Bs]);
-              num = rounds * cap * hide;
-              den = G * x;
-            } else {
-              num = hide;
-              den = x;
-            }
-            const float F = (float)num / (float)den;
-            sc = (B > 0) ? Ed * F : __builtin_huge_valf();
-            if (L.score && in) L.score[eidx] = sc;
-          }
-          ok = B > 0;
-        } else {
-          sc = Kv[i];
-          ok = in && sc < __builtin_huge_valf();
-        }
-        if constexpr (TOPK) {
-          const uint32_t kk = order_key(sc);
-          const bool cand = ok && kk <= sel.theta;
-          const uint64_t key = ((uint64_t)kk << 32) | (uint32_t)(eidx - s0);
-          offer(sel, cand, key, k, lane);
-        }
-      }
-    }
+    Evaluator<MODE, HAS_GRID, TOPK> ev{L, tb, pc, sel, lane};
+    ev.run(e, pe);
 
     if constexpr (TOPK) {
       const uint64_t mine = select_k(sel, k, lane);
       if (e == s0 && pe == s1) {
-        write_final(mine, k, lane, v, L.topk_idx, L.topk_val);
+        write_final(mine, k, lane, v, L.topk_idx, L.topk_val, MODE == Mode::Keys ? L.keys : nullptr, s0);
       } else {
         const int64_t slot = 2 * wt + (e == t0 ? 0 : 1);
         if (lane < k) L.frag[slot * k + lane] = mine;
@@ -404,12 +630,11 @@ __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
   const int64_t T = L.tile;
   Selector sel;
   sel.buf = cand[w];
-  for (int64_t v = (int64_t)blockIdx.x * kWavesPerBlock + w; v < L.n_var;
-       v += (int64_t)gridDim.x * kWavesPerBlock) {
-    const int64_t s0 = clamp_off(L.cfg.seg[v], n_evals);
-    const int64_t s1 = clamp_off(L.cfg.seg[v + 1], n_evals);
+  for (int64_t v = (int64_t)blockIdx.x * kWavesPerBlock + w; v < L.n_var; v += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t s0 = uniform64(clamp_off(L.cfg.seg[v], n_evals));
+    const int64_t s1 = uniform64(clamp_off(L.cfg.seg[v + 1], n_evals));
     if (s1 <= s0) {
-      write_final(kKeyNone, k, lane, v, L.topk_idx, L.topk_val);
+      write_final(kKeyNone, k, lane, v, L.topk_idx, L.topk_val, nullptr, 0);
       continue;
     }
     const int64_t ta = s0 / T, tb = (s1 - 1) / T;
@@ -426,11 +651,13 @@ __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
         const int64_t slot = (t == ta && s0 != ta * T) ? 2 * t + 1 : 2 * t;
         if (slot < 2 * L.n_tiles) key = L.frag[slot * k + r];
       }
-      const bool cand_ok = key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta;
-      offer(sel, cand_ok, key, k, lane);
+      make_room(sel, 64, k, lane);
+      const bool cand[1] = {key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta};
+      const uint64_t keys1[1] = {key};
+      offer<1>(sel, cand, keys1);
     }
     const uint64_t mine = select_k(sel, k, lane);
-    write_final(mine, k, lane, v, L.topk_idx, L.topk_val);
+    write_final(mine, k, lane, v, L.topk_idx, L.topk_val, L.keys, s0);
   }
 }
 
@@ -438,8 +665,7 @@ template <Mode M, bool G, bool K>
 hipError_t launch_one(const EvalLaunch &L, hipStream_t stream) {
   const int64_t blocks = (L.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
-  size_t dyn = 0;
-  if (M == Mode::Model) dyn = (((size_t)(L.arch.nr + 1) * (size_t)(L.arch.nw + 1)) + 15) & ~(size_t)15;
+  const size_t dyn = M == Mode::Model ? (size_t)L.dyn_lds_bytes : 0;
   hipLaunchKernelGGL((sa_eval_kernel<M, G, K>), dim3((uint32_t)blocks), dim3(kBlockThreads), dyn, stream, L);
   return hipGetLastError();
 }

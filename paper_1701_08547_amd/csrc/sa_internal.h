@@ -13,13 +13,13 @@ constexpr int kWaveSize = 64;           // gfx950 wavefront
 constexpr int kWavesPerBlock = 4;       // independent waves per workgroup
 constexpr int kBlockThreads = kWaveSize * kWavesPerBlock;
 constexpr int kItems = 4;               // rows of 64 evaluations in flight per wave
-constexpr int kCandCap = 256;           // candidate keys buffered per wave (LDS)
+constexpr int kCandCap = 512;           // candidate keys buffered per wave (LDS)
 constexpr int kTabBMax = 16384;         // occupancy table entries (bytes, dynamic LDS)
 constexpr int kMaxWB = 64;              // largest waves-per-block the tables hold
 constexpr int kMaxUnroll = 64;
 constexpr int32_t kTileMin = 1024;      // evaluations per wave-tile, smallest
 constexpr int32_t kTileMax = 65536;
-constexpr int32_t kTileDefault = 4096;
+constexpr int32_t kTileDefault = 8192;
 
 // Descriptor as the kernels read it: the public fields plus the sizes and
 // division constants the host derives from them once per call.
@@ -29,8 +29,8 @@ struct KArch {
   float cfp, cint, cmem, cctrl, csync, creg;
   int32_t nw;      // ceil(max_threads / ws): largest W_B
   int32_t nr;      // ceil(max_vgprs / vgpr_gran): largest register granule count
-  uint32_t m_ws;   // floor(2^32 / ws) + 1   (exact floor division for n < 2^17)
-  uint32_t m_gran; // floor(2^32 / vgpr_gran) + 1, or 0 when vgpr_gran == 1
+  int32_t ws_shift;    // log2(ws)         (wave size is a power of two)
+  int32_t gran_shift;  // log2(vgpr_gran)  (register granule is a power of two)
 };
 
 struct KVariants {
@@ -58,6 +58,9 @@ struct EvalLaunch {
   int32_t tile;           // evaluations per wave-tile
   int64_t n_tiles;
   int32_t need_score;
+  int32_t vec;            // every streamed column 16-byte aligned: vector loads
+  int32_t tab_wtot_off;   // dynamic LDS layout of the occupancy tables
+  int32_t dyn_lds_bytes;
 };
 
 enum class Mode { Model, Keys };

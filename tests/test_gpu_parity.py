@@ -168,6 +168,8 @@ def test_topk_entry_point_keys():
     keys[g.random(n) < 0.02] = -np.inf
     keys[g.random(n) < 0.02] = np.nan
     keys[g.random(n) < 0.3] = np.float32(1.5)  # ties
+    keys[g.random(n) < 0.05] = np.float32(-0.0)  # signed zeros tie with +0
+    keys[g.random(n) < 0.05] = np.float32(0.0)
     for k in (1, 8, 33):
         say("case sa_topk", n, "k", k)
         ridx, rval = oracle.topk(keys, seg, k)
@@ -179,6 +181,24 @@ def test_topk_entry_point_keys():
             api.set_tile(0)
         assert np.array_equal(ridx, idx.cpu().numpy())
         assert np.array_equal(rval.view(np.uint32), val.cpu().numpy().view(np.uint32))
+
+
+def test_unaligned_columns_take_the_masked_path():
+    """Columns that are not 16-byte aligned (views at an odd offset) give the
+    same results through the scalar path."""
+    b = workloads.custom_batch(12, [700, 5000, 33], with_grid=True, name="unaligned")
+    a = oracle.arch_cdna4()
+    ref = oracle.run(a, b.variants, b.configs(), k=8)
+    var, cfg = api.device_batch(b)
+    for key in ("block", "unroll", "regs", "grid"):
+        big = torch.empty(cfg[key].numel() + 1, dtype=torch.int32, device=cfg[key].device)
+        big[1:] = cfg[key]
+        cfg[key] = big[1:]
+    say("case unaligned", b.n_evals)
+    out = api.score(a, var, cfg, k=8)
+    torch.cuda.synchronize()
+    got = {key: t.cpu().numpy() for key, t in out.items()}
+    assert_parity(ref, got)
 
 
 def test_empty_batches():
