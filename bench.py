@@ -40,7 +40,34 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c1.json"),
                    help="JSON with measured HBM bytes per launch of the evaluation kernel")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain device copy of 256,000 KiB (counter calibration under rocprofv3)")
     return p.parse_args()
+
+
+def source_digest() -> str:
+    """Digest of the kernel sources: a traffic figure measured for other
+    sources is not reported."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1701_08547_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def copy_calibration():
+    import torch
+
+    n = 256000 * 1024 // 4  # 256,000 KiB of float32
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 5}), flush=True)
 
 
 def cpu_baseline(batch, seconds: float) -> dict:
@@ -63,6 +90,9 @@ def cpu_baseline(batch, seconds: float) -> dict:
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the model's batch shards by variant with no "
               "exchange but the top-k gather; see the design notes); run with --gpus 1", file=sys.stderr)
@@ -112,7 +142,9 @@ def main():
     traffic = None
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+            t = json.load(f)
+        if t.get("source_digest") == source_digest():
+            traffic = t.get("bytes_per_launch")
 
     line = {
         "metric": METRIC,

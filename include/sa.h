@@ -173,8 +173,8 @@ sa_status sa_arch_default_gfx950(int device, sa_arch *out);
 sa_status sa_arch_validate(const sa_arch *arch);
 
 /* Bytes of workspace sa_score / sa_topk need for this problem size (an upper
- * bound over every tile size the library may pick).  0 when k == 0.
- * `flags` is reserved (pass 0). */
+ * bound over every tile size the library may pick).  0 when k <= 0 or
+ * n_evals == 0.  `flags` is reserved (pass 0). */
 size_t sa_workspace_bytes(int64_t n_variants, int64_t n_evals, int32_t k, int32_t flags);
 
 /*
@@ -206,6 +206,8 @@ sa_status sa_occupancy(const sa_arch *arch, const sa_variants *variants, const s
  *   mlp       must be NULL (plain static model).
  *   workspace device buffer of sa_workspace_bytes(...) bytes (may be NULL
  *             when no top-k is asked for).  Contents need no initialisation.
+ *             Segments that span several wave-tiles leave per-tile partial
+ *             results there, combined by a second kernel on the same stream.
  * Calls that share a workspace must be ordered on one stream.
  */
 sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,

@@ -130,6 +130,17 @@ size_t frag_bytes(int64_t n_evals, int32_t tile, int32_t k) {
   return (size_t)(2 * tiles * (int64_t)k * (int64_t)sizeof(uint64_t));
 }
 
+// Point the launch at its workspace: the fragment slots.
+sa_status bind_workspace(sa::EvalLaunch &L, void *workspace, size_t workspace_bytes) {
+  const size_t need = frag_bytes(L.n_evals, L.tile, L.k);
+  if (need == 0) return SA_OK;
+  if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+  if (!aligned(workspace, 256)) return fail(SA_ERR_ALIGN, "workspace not 256-byte aligned");
+  if (workspace_bytes < need) return fail(SA_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, need);
+  L.frag = (uint64_t *)workspace;
+  return SA_OK;
+}
+
 sa_status check_variants(const sa_variants *v, int64_t n_var) {
   if (!v) return fail(SA_ERR_ARG, "variants is NULL");
   if (n_var == 0) return SA_OK;
@@ -232,11 +243,11 @@ sa_status sa_arch_default_gfx950(int device, sa_arch *out) {
 sa_status sa_arch_validate(const sa_arch *arch) { return check_arch(arch); }
 
 size_t sa_workspace_bytes(int64_t n_variants, int64_t n_evals, int32_t k, int32_t flags) {
-  (void)n_variants;
   (void)flags;
+  (void)n_variants;
   if (k <= 0 || n_evals <= 0) return 0;
   if (k > SA_K_MAX) k = SA_K_MAX;
-  return frag_bytes(n_evals, sa::kTileMin, k) + 256;
+  return frag_bytes(n_evals, sa::kTileMin, k);
 }
 
 sa_status sa_set_tile(int32_t evals_per_wave) {
@@ -312,14 +323,8 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   L.need_score = (score || topk) ? 1 : 0;
   L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves, score}) ? 1 : 0;
   set_lds_layout(L);
-  if (topk) {
-    const size_t need = frag_bytes(n_evals, L.tile, k);
-    if (need > 0) {
-      if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
-      if (!aligned(workspace, 256)) return fail(SA_ERR_ALIGN, "workspace not 256-byte aligned");
-      if (workspace_bytes < need) return fail(SA_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, need);
-    }
-    L.frag = (uint64_t *)workspace;
+  if (topk && n_variants > 0) {
+    if ((st = bind_workspace(L, workspace, workspace_bytes)) != SA_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
   if (n_evals > 0) {
@@ -355,13 +360,9 @@ sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int
   L.tile = pick_tile(n_evals);
   L.n_tiles = ceil_div(n_evals, L.tile);
   L.vec = all16({keys}) ? 1 : 0;
-  const size_t need = frag_bytes(n_evals, L.tile, k);
-  if (need > 0) {
-    if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
-    if (!aligned(workspace, 256)) return fail(SA_ERR_ALIGN, "workspace not 256-byte aligned");
-    if (workspace_bytes < need) return fail(SA_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, need);
+  if (n_variants > 0) {
+    if ((st = bind_workspace(L, workspace, workspace_bytes)) != SA_OK) return st;
   }
-  L.frag = (uint64_t *)workspace;
   hipStream_t s = (hipStream_t)stream;
   if (n_evals > 0) {
     hipError_t e = sa::launch_eval(L, sa::Mode::Keys, false, true, s);

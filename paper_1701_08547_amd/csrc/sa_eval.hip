@@ -619,45 +619,51 @@ void sa_eval_kernel(EvalLaunch L) {
   }
 }
 
-// Combine the fragments of segments that span several wave-tiles, and write
-// the padding row of empty segments.  One wave per variant.
+// Combine the k-key fragments of every piece of segment v (which spans the
+// wave-tiles ta .. tb, ta < tb) into its final row.
+__device__ void merge_segment(const EvalLaunch &L, Selector &sel, int64_t v, int64_t s0, int64_t s1, int lane) {
+  const int k = L.k;
+  const int64_t T = L.tile;
+  const int64_t ta = s0 / T, tb = (s1 - 1) / T;
+  sel.count = 0;
+  sel.theta = kThetaInit;
+  const int64_t n_keys = (tb - ta + 1) * k;
+  for (int64_t base = 0; base < n_keys; base += 64) {
+    const int64_t j = base + lane;
+    uint64_t key = kKeyNone;
+    if (j < n_keys) {
+      const int64_t p = j / k, r = j - p * k;
+      const int64_t t = ta + p;
+      const int64_t slot = (t == ta && s0 != ta * T) ? 2 * t + 1 : 2 * t;
+      if (slot < 2 * L.n_tiles) key = L.frag[slot * k + r];
+    }
+    make_room(sel, 64, k, lane);
+    const bool cand[1] = {key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta};
+    const uint64_t keys1[1] = {key};
+    offer<1>(sel, cand, keys1);
+  }
+  const uint64_t mine = select_k(sel, k, lane);
+  write_final(mine, k, lane, v, L.topk_idx, L.topk_val, L.keys, s0);
+}
+
+// Second pass of the two-launch path: merge segments that span wave-tiles
+// and write the padding row of empty segments.  One wave per variant.
 __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
   __shared__ uint64_t cand[kWavesPerBlock][kCandCap];
   const int lane = lane_id();
   const int w = threadIdx.x / kWaveSize;
   const int64_t n_evals = L.n_evals;
-  const int k = L.k;
-  const int64_t T = L.tile;
   Selector sel;
   sel.buf = cand[w];
   for (int64_t v = (int64_t)blockIdx.x * kWavesPerBlock + w; v < L.n_var; v += (int64_t)gridDim.x * kWavesPerBlock) {
     const int64_t s0 = uniform64(clamp_off(L.cfg.seg[v], n_evals));
     const int64_t s1 = uniform64(clamp_off(L.cfg.seg[v + 1], n_evals));
     if (s1 <= s0) {
-      write_final(kKeyNone, k, lane, v, L.topk_idx, L.topk_val, nullptr, 0);
+      write_final(kKeyNone, L.k, lane, v, L.topk_idx, L.topk_val, nullptr, 0);
       continue;
     }
-    const int64_t ta = s0 / T, tb = (s1 - 1) / T;
-    if (ta == tb) continue;  // whole segment inside one wave-tile: already final
-    sel.count = 0;
-    sel.theta = kThetaInit;
-    const int64_t n_keys = (tb - ta + 1) * k;
-    for (int64_t base = 0; base < n_keys; base += 64) {
-      const int64_t j = base + lane;
-      uint64_t key = kKeyNone;
-      if (j < n_keys) {
-        const int64_t p = j / k, r = j - p * k;
-        const int64_t t = ta + p;
-        const int64_t slot = (t == ta && s0 != ta * T) ? 2 * t + 1 : 2 * t;
-        if (slot < 2 * L.n_tiles) key = L.frag[slot * k + r];
-      }
-      make_room(sel, 64, k, lane);
-      const bool cand[1] = {key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta};
-      const uint64_t keys1[1] = {key};
-      offer<1>(sel, cand, keys1);
-    }
-    const uint64_t mine = select_k(sel, k, lane);
-    write_final(mine, k, lane, v, L.topk_idx, L.topk_val, L.keys, s0);
+    if (s0 / L.tile == (s1 - 1) / L.tile) continue;  // inside one wave-tile: already final
+    merge_segment(L, sel, v, s0, s1, lane);
   }
 }
 
