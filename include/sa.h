@@ -225,10 +225,73 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
 sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int64_t n_evals, int32_t k,
                   int32_t *idx, float *val, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Tile size (evaluations per wave) the next calls on this thread use; 0
- * restores the library's choice.  Must be a multiple of 256 in
- * [1024, 65536].  Used by the tile autotuner. */
+/* Tile size (evaluations per wave) the next sa_score / sa_occupancy /
+ * sa_topk calls on this thread use; 0 restores the library's choice.  Must
+ * be a multiple of 256 in [1024, 65536]. */
 sa_status sa_set_tile(int32_t evals_per_wave);
+
+/*
+ * Plans: batches of uneven search spaces (segments of very different
+ * lengths) scored by one persistent kernel launch.
+ *
+ * A plan is a host object made once per CSR layout from a HOST copy of the
+ * segment offsets.  Segments longer than `tile` are cut into workgroup items
+ * of up to tile x waves_per_block evaluations, one part per wave, whose
+ * per-wave top-k meet in LDS; shorter segments are packed whole into items
+ * and spread over the waves.  A segment longer than one item leaves one
+ * k-key fragment per item in the workspace, combined by a second small
+ * kernel only when such segments exist.  Shape: tile a multiple of 256 in
+ * [256, 2^20]; items_per_lane 1, 2 or 4 (consecutive evaluations per lane per
+ * load: 4-, 8- or 16-byte accesses); waves_per_block 4, 8 or 16.
+ *
+ * sa_plan_create validates the offsets (seg[0] = 0, non-decreasing,
+ * seg[n_variants] = n_evals), allocates the plan's device buffer and copies
+ * it synchronously: it is a set-up call, not for graph capture.
+ * sa_plan_score / sa_plan_topk are asynchronous, allocation-free and
+ * capturable, like sa_score / sa_topk; `seg` passed to them must hold the
+ * same offsets on the device.
+ */
+typedef struct sa_plan sa_plan;
+typedef struct sa_plan_shape {
+  int32_t tile;            /* evaluations per wave part / per wave of packing */
+  int32_t items_per_lane;  /* 1, 2, 4                                         */
+  int32_t waves_per_block; /* 4, 8, 16                                        */
+} sa_plan_shape;
+
+sa_status sa_plan_create(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k,
+                         const sa_plan_shape *shape /* NULL = 4096, 4, 4 */, sa_plan **out);
+sa_status sa_plan_destroy(sa_plan *plan);
+/* The plan's decomposition computed on the host only (no device needed):
+ * counts, and when the arrays are non-NULL, items (n_items x {kind, slot,
+ * v}), waves (n_items x waves_per_block x {e0, e1, v0, v1}) and splits
+ * (n_splits x {v, first_slot, n_slots}).  Validates like sa_plan_create. */
+sa_status sa_plan_layout(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, const sa_plan_shape *shape,
+                         int64_t *n_items, int64_t *n_splits, int64_t *n_slots, int64_t *items, int64_t *waves,
+                         int64_t *splits);
+/* Shape, item and split counts, and the workspace bytes the plan needs. */
+sa_status sa_plan_info(const sa_plan *plan, sa_plan_shape *shape, int64_t *n_items, int64_t *n_splits,
+                       size_t *workspace_bytes);
+/* sa_score over a plan: same outputs and conventions; k is the plan's. */
+sa_status sa_plan_score(const sa_plan *plan, const sa_arch *arch, const sa_variants *variants,
+                        const sa_configs *configs, float *score, int32_t *occ_waves, int32_t *topk_idx,
+                        float *topk_val, void *workspace, size_t workspace_bytes, void *stream);
+/* sa_topk over a plan. */
+sa_status sa_plan_topk(const sa_plan *plan, const float *keys, const int64_t *seg, int32_t *idx, float *val,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Launch-shape autotuner: times sa_plan_score for every shape in
+ * {1024, 2048, 4096, 8192} x {1, 2, 4} x {4, 8, 16} on the caller's buffers
+ * (outputs are overwritten), `reps` timed runs each after one warm-up, on
+ * `stream`, and returns the fastest shape and its median milliseconds.
+ * Synchronises; creates and destroys plans.  The workspace must hold
+ * sa_plan_autotune_workspace_bytes(...) bytes.
+ */
+size_t sa_plan_autotune_workspace_bytes(int64_t n_variants, int64_t n_evals, int32_t k);
+sa_status sa_plan_autotune(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k,
+                           const sa_arch *arch, const sa_variants *variants, const sa_configs *configs, float *score,
+                           int32_t *occ_waves, int32_t *topk_idx, float *topk_val, void *workspace,
+                           size_t workspace_bytes, void *stream, int32_t reps, sa_plan_shape *best, float *best_ms);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,8 @@ STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_ARG", -2: "SA_ERR_ALIGN", -3: "SA_ERR_NO
 EXPORTED = (
     "sa_status_string", "sa_last_error", "sa_arch_gfx950", "sa_arch_default_gfx950", "sa_arch_validate",
     "sa_workspace_bytes", "sa_occupancy", "sa_score", "sa_topk", "sa_set_tile",
+    "sa_plan_create", "sa_plan_destroy", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
+    "sa_plan_autotune_workspace_bytes", "sa_plan_autotune",
 )
 
 
@@ -49,6 +51,10 @@ class SaVariants(ctypes.Structure):
 
 class SaConfigs(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in CONFIG_COLUMNS]
+
+
+class SaPlanShape(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("items_per_lane", ctypes.c_int32), ("waves_per_block", ctypes.c_int32)]
 
 
 class SAError(RuntimeError):
@@ -92,6 +98,24 @@ def lib():
             L.sa_topk.restype = i32
             L.sa_set_tile.argtypes = [i32]
             L.sa_set_tile.restype = i32
+            PS = P(SaPlanShape)
+            L.sa_plan_create.argtypes = [vp, i64, i64, i32, PS, P(vp)]
+            L.sa_plan_create.restype = i32
+            L.sa_plan_destroy.argtypes = [vp]
+            L.sa_plan_destroy.restype = i32
+            L.sa_plan_layout.argtypes = [vp, i64, i64, PS, P(i64), P(i64), P(i64), vp, vp, vp]
+            L.sa_plan_layout.restype = i32
+            L.sa_plan_info.argtypes = [vp, PS, P(i64), P(i64), P(sz)]
+            L.sa_plan_info.restype = i32
+            L.sa_plan_score.argtypes = [vp, P(SaArch), P(SaVariants), P(SaConfigs), vp, vp, vp, vp, vp, sz, vp]
+            L.sa_plan_score.restype = i32
+            L.sa_plan_topk.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+            L.sa_plan_topk.restype = i32
+            L.sa_plan_autotune_workspace_bytes.argtypes = [i64, i64, i32]
+            L.sa_plan_autotune_workspace_bytes.restype = sz
+            L.sa_plan_autotune.argtypes = [vp, i64, i64, i32, P(SaArch), P(SaVariants), P(SaConfigs), vp, vp, vp, vp,
+                                           vp, sz, vp, i32, PS, P(ctypes.c_float)]
+            L.sa_plan_autotune.restype = i32
             _lib = L
     return _lib
 
@@ -293,3 +317,134 @@ def device_batch(batch, device="cuda") -> tuple[dict, dict]:
         a = getattr(batch, f)
         cfg[f] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
     return var, cfg
+
+
+# ------------------------------------------------------------------ plans
+
+
+def _shape(shape):
+    if shape is None:
+        return None
+    if isinstance(shape, SaPlanShape):
+        return shape
+    t, i, w = shape
+    return SaPlanShape(int(t), int(i), int(w))
+
+
+def _seg_host(seg) -> np.ndarray:
+    if hasattr(seg, "detach"):
+        seg = seg.detach().cpu().numpy()
+    return np.ascontiguousarray(seg, dtype=np.int64)
+
+
+def plan_layout(seg, shape=None) -> dict:
+    """The decomposition a plan would use, computed on the host."""
+    sh = _seg_host(seg)
+    n_var, n_evals = sh.shape[0] - 1, int(sh[-1])
+    ni, ns, nsl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    s = _shape(shape)
+    sp = ctypes.byref(s) if s is not None else None
+    vp = sh.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().sa_plan_layout(vp, n_var, n_evals, sp, ctypes.byref(ni), ctypes.byref(ns), ctypes.byref(nsl),
+                                None, None, None))
+    wpb = (s.waves_per_block if s is not None else 4)
+    items = np.zeros((ni.value, 3), np.int64)
+    waves = np.zeros((ni.value, wpb, 4), np.int64)
+    splits = np.zeros((ns.value, 3), np.int64)
+    _check(lib().sa_plan_layout(vp, n_var, n_evals, sp, ctypes.byref(ni), ctypes.byref(ns), ctypes.byref(nsl),
+                                items.ctypes.data_as(ctypes.c_void_p), waves.ctypes.data_as(ctypes.c_void_p),
+                                splits.ctypes.data_as(ctypes.c_void_p)))
+    return {"items": items, "waves": waves, "splits": splits, "n_slots": nsl.value, "wpb": wpb}
+
+
+class Plan:
+    """A persistent-kernel plan for one CSR layout (sa_plan_*)."""
+
+    def __init__(self, seg, k: int = 8, shape=None):
+        sh = _seg_host(seg)
+        self.n_var, self.n_evals, self.k = sh.shape[0] - 1, int(sh[-1]), int(k)
+        h = ctypes.c_void_p()
+        s = _shape(shape)
+        _check(lib().sa_plan_create(sh.ctypes.data_as(ctypes.c_void_p), self.n_var, self.n_evals, self.k,
+                                    ctypes.byref(s) if s is not None else None, ctypes.byref(h)))
+        self._h = h
+        info_shape = SaPlanShape()
+        ni, ns, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib().sa_plan_info(self._h, ctypes.byref(info_shape), ctypes.byref(ni), ctypes.byref(ns),
+                                  ctypes.byref(wb)))
+        self.shape = (info_shape.tile, info_shape.items_per_lane, info_shape.waves_per_block)
+        self.n_items, self.n_splits, self.workspace_bytes = ni.value, ns.value, wb.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def score(self, arch: dict, variants: dict, configs: dict, *, want_score=True, want_occ=True, want_topk=True,
+              outputs: dict | None = None, workspace: Workspace | None = None, stream=None) -> dict:
+        torch = _torch()
+        dev = configs["seg"].device
+        o = dict(outputs or {})
+        if want_occ and o.get("occ") is None:
+            o["occ"] = torch.empty(self.n_evals, dtype=torch.int32, device=dev)
+        if want_score and o.get("score") is None:
+            o["score"] = torch.empty(self.n_evals, dtype=torch.float32, device=dev)
+        if want_topk:
+            if o.get("idx") is None:
+                o["idx"] = torch.empty((self.n_var, self.k), dtype=torch.int32, device=dev)
+            if o.get("val") is None:
+                o["val"] = torch.empty((self.n_var, self.k), dtype=torch.float32, device=dev)
+        if workspace is None:
+            workspace = Workspace(self.workspace_bytes, dev)
+        for key in ("occ", "score", "idx", "val"):
+            o.setdefault(key, None)
+        a = _arch_struct(arch)
+        _check(lib().sa_plan_score(self._h, ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
+                                   ctypes.byref(_configs_struct(configs)),
+                                   _ptr(o["score"] if want_score else None, torch.float32, "score"),
+                                   _ptr(o["occ"] if want_occ else None, torch.int32, "occ"),
+                                   _ptr(o["idx"] if want_topk else None, torch.int32, "idx"),
+                                   _ptr(o["val"] if want_topk else None, torch.float32, "val"),
+                                   workspace.ptr, workspace.nbytes, _stream(stream)))
+        return o
+
+    def topk(self, keys, seg, *, workspace: Workspace | None = None, stream=None):
+        torch = _torch()
+        idx = torch.empty((self.n_var, self.k), dtype=torch.int32, device=seg.device)
+        val = torch.empty((self.n_var, self.k), dtype=torch.float32, device=seg.device)
+        if workspace is None:
+            workspace = Workspace(self.workspace_bytes, seg.device)
+        _check(lib().sa_plan_topk(self._h, _ptr(keys, torch.float32, "keys"), _ptr(seg, torch.int64, "seg"),
+                                  _ptr(idx, torch.int32, "idx"), _ptr(val, torch.float32, "val"), workspace.ptr,
+                                  workspace.nbytes, _stream(stream)))
+        return idx, val
+
+
+def autotune(arch: dict, variants: dict, configs: dict, k: int = 8, reps: int = 3, outputs: dict | None = None,
+             stream=None):
+    """Fastest plan shape for this batch (sa_plan_autotune): (shape, ms)."""
+    torch = _torch()
+    sh = _seg_host(configs["seg"])
+    n_var, n_evals = sh.shape[0] - 1, int(sh[-1])
+    dev = configs["seg"].device
+    o = dict(outputs or {})
+    o.setdefault("occ", torch.empty(n_evals, dtype=torch.int32, device=dev))
+    o.setdefault("score", torch.empty(n_evals, dtype=torch.float32, device=dev))
+    o.setdefault("idx", torch.empty((n_var, k), dtype=torch.int32, device=dev))
+    o.setdefault("val", torch.empty((n_var, k), dtype=torch.float32, device=dev))
+    ws = Workspace(int(lib().sa_plan_autotune_workspace_bytes(n_var, n_evals, k)), dev)
+    best = SaPlanShape()
+    ms = ctypes.c_float()
+    a = _arch_struct(arch)
+    _check(lib().sa_plan_autotune(sh.ctypes.data_as(ctypes.c_void_p), n_var, n_evals, int(k), ctypes.byref(a),
+                                  ctypes.byref(_variants_struct(variants)), ctypes.byref(_configs_struct(configs)),
+                                  _ptr(o["score"], torch.float32), _ptr(o["occ"], torch.int32),
+                                  _ptr(o["idx"], torch.int32), _ptr(o["val"], torch.float32), ws.ptr, ws.nbytes,
+                                  _stream(stream), int(reps), ctypes.byref(best), ctypes.byref(ms)))
+    return (best.tile, best.items_per_lane, best.waves_per_block), float(ms.value)

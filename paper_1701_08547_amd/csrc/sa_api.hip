@@ -13,9 +13,11 @@
 #include "sa_internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
 thread_local int32_t g_tile = 0;
+}  // namespace
+
+namespace sa_detail {
 
 sa_status fail(sa_status st, const char *fmt, ...) {
   va_list ap;
@@ -177,7 +179,9 @@ sa_status hip_fail(hipError_t e, const char *what) {
   return fail(SA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace
+}  // namespace sa_detail
+
+using namespace sa_detail;
 
 extern "C" {
 

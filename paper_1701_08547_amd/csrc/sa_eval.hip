@@ -36,17 +36,12 @@ namespace {
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr uint32_t kThetaInit = 0xFF7FFFFFu;  // order key of FLT_MAX
 constexpr int32_t kUnlimited = 1 << 30;
-constexpr int kChunk = 64 * 4;                // evaluations per vector chunk
-#ifndef SA_PREFETCH
-#define SA_PREFETCH 1
-#endif
 #ifndef SA_NT_STORE
 #define SA_NT_STORE 1
 #endif
 #ifndef SA_WAVES_PER_EU
 #define SA_WAVES_PER_EU 4
 #endif
-constexpr int kPrefetch = SA_PREFETCH;        // chunks of loads in flight per wave
 
 typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
@@ -326,8 +321,45 @@ __device__ __forceinline__ void eval_cfg(const KArch &A, const Tables &tb, const
   }
 }
 
-template <Mode MODE, bool HAS_GRID, bool TOPK>
+// N consecutive int32 / binary32 values of one lane (one 4N-byte access).
+template <int N>
+struct alignas(4 * N) IVec {
+  int32_t v[N];
+};
+template <int N>
+struct alignas(4 * N) FVec {
+  float v[N];
+};
+
+template <int N>
+__device__ __forceinline__ void store_n(int32_t *p, const int32_t (&x)[N]) {
+  if constexpr (N == 4) {
+    store4(p, x[0], x[1], x[2], x[3]);
+  } else {
+    IVec<N> t;
+#pragma unroll
+    for (int i = 0; i < N; ++i) t.v[i] = x[i];
+    *(IVec<N> *)p = t;
+  }
+}
+template <int N>
+__device__ __forceinline__ void store_n(float *p, const float (&x)[N]) {
+  if constexpr (N == 4) {
+    store4(p, x[0], x[1], x[2], x[3]);
+  } else {
+    FVec<N> t;
+#pragma unroll
+    for (int i = 0; i < N; ++i) t.v[i] = x[i];
+    *(FVec<N> *)p = t;
+  }
+}
+
+// Streams one piece [e, pe) of one segment.  ITEMS consecutive evaluations
+// per lane per chunk (chunk = 64 ITEMS evaluations), one chunk of loads in
+// flight ahead of the one being evaluated.
+template <Mode MODE, bool HAS_GRID, bool TOPK, int ITEMS>
 struct Evaluator {
+  static constexpr int kC = 64 * ITEMS;
   const EvalLaunch &L;
   const Tables &tb;
   const Piece &pc;
@@ -336,7 +368,7 @@ struct Evaluator {
 
   // Masked rows over [base, end): lane l takes base + 64 i + l.  end - base <= 256.
   __device__ __forceinline__ void masked(int64_t base, int64_t end) {
-    if constexpr (TOPK) make_room(sel, kChunk, L.k, lane);
+    if constexpr (TOPK) make_room(sel, 256, L.k, lane);
     const int rem = (int)(end - base);
     int32_t Tv[4], Uv[4], Rv[4], Gv[4];
     float Kv[4];
@@ -380,63 +412,62 @@ struct Evaluator {
   }
 
   struct Cols {
-    int4 T, U, R, G;
-    float4 K;
+    IVec<ITEMS> T, U, R, G;
+    FVec<ITEMS> K;
   };
 
   __device__ __forceinline__ Cols load_chunk(int64_t base) const {
     Cols c;
-    const int64_t o = base + 4 * lane;
+    const int64_t o = base + ITEMS * lane;
     if constexpr (MODE == Mode::Model) {
-      c.T = *(const int4 *)(L.cfg.block + o);
-      c.U = *(const int4 *)(L.cfg.unroll + o);
-      c.R = *(const int4 *)(L.cfg.regs + o);
-      if (HAS_GRID) c.G = *(const int4 *)(L.cfg.grid + o);
-      else c.G = make_int4(1, 1, 1, 1);
+      c.T = *(const IVec<ITEMS> *)(L.cfg.block + o);
+      c.U = *(const IVec<ITEMS> *)(L.cfg.unroll + o);
+      c.R = *(const IVec<ITEMS> *)(L.cfg.regs + o);
+      if (HAS_GRID) {
+        c.G = *(const IVec<ITEMS> *)(L.cfg.grid + o);
+      } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) c.G.v[i] = 1;
+      }
     } else {
-      c.K = *(const float4 *)(L.keys + o);
+      c.K = *(const FVec<ITEMS> *)(L.keys + o);
     }
     return c;
   }
 
   __device__ __forceinline__ void chunk(const Cols &c, int64_t base) {
-    const int64_t o = base + 4 * lane;
-    float sc[4];
-    int32_t W[4];
-    bool ok[4];
+    const int64_t o = base + ITEMS * lane;
+    float sc[ITEMS];
+    int32_t W[ITEMS];
+    bool ok[ITEMS];
     if constexpr (MODE == Mode::Model) {
-      const int32_t Ts[4] = {c.T.x, c.T.y, c.T.z, c.T.w};
-      const int32_t Us[4] = {c.U.x, c.U.y, c.U.z, c.U.w};
-      const int32_t Rs[4] = {c.R.x, c.R.y, c.R.z, c.R.w};
-      const int32_t Gs[4] = {c.G.x, c.G.y, c.G.z, c.G.w};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        eval_cfg<HAS_GRID>(L.arch, tb, pc, Ts[i], Us[i], Rs[i], Gs[i], true, L.need_score, W[i], sc[i]);
+      for (int i = 0; i < ITEMS; ++i) {
+        eval_cfg<HAS_GRID>(L.arch, tb, pc, c.T.v[i], c.U.v[i], c.R.v[i], c.G.v[i], true, L.need_score, W[i], sc[i]);
         ok[i] = W[i] > 0;
       }
-      if (L.occ) store4(L.occ + o, W[0], W[1], W[2], W[3]);
-      if (L.score) store4(L.score + o, sc[0], sc[1], sc[2], sc[3]);
+      if (L.occ) store_n<ITEMS>(L.occ + o, W);
+      if (L.score) store_n<ITEMS>(L.score + o, sc);
     } else {
-      sc[0] = c.K.x;
-      sc[1] = c.K.y;
-      sc[2] = c.K.z;
-      sc[3] = c.K.w;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ok[i] = sc[i] < __builtin_huge_valf();
+      for (int i = 0; i < ITEMS; ++i) {
+        sc[i] = c.K.v[i];
+        ok[i] = sc[i] < __builtin_huge_valf();
+      }
     }
     if constexpr (TOPK) {
       const uint32_t li = (uint32_t)(o - pc.s0);
-      bool cand[4];
-      uint64_t key[4];
+      bool cand[ITEMS];
+      uint64_t key[ITEMS];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < ITEMS; ++i) {
         // model scores are +0 .. +inf: the key is the bit pattern with the
         // sign bit set, and +inf's key lies above every threshold
         const uint32_t kk = MODE == Mode::Model ? (__float_as_uint(sc[i]) | 0x80000000u) : order_key(sc[i]);
         cand[i] = MODE == Mode::Model ? kk <= sel.theta : (ok[i] && kk <= sel.theta);
         key[i] = ((uint64_t)kk << 32) | (li + (uint32_t)i);
       }
-      offer<4>(sel, cand, key);
+      offer<ITEMS>(sel, cand, key);
     }
   }
 
@@ -445,37 +476,123 @@ struct Evaluator {
   __device__ void run(int64_t e, int64_t pe) {
     int64_t body = e;
     if (L.vec) {
-      int64_t a0 = (e + 3) & ~(int64_t)3;
+      int64_t a0 = (e + ITEMS - 1) & ~(int64_t)(ITEMS - 1);
       a0 = a0 < pe ? a0 : pe;
       if (a0 > e) masked(e, a0);
       body = a0;
-      const int64_t nfull = (pe - a0) / kChunk;
+      const int64_t nfull = (pe - a0) / kC;
       if (nfull > 0) {
-        // kPrefetch chunks in flight: q[0] is evaluated while q[1..] and the
-        // newly issued chunk are still loading
-        Cols q[kPrefetch];
-#pragma unroll
-        for (int d = 0; d < kPrefetch; ++d)
-          if (d < nfull) q[d] = load_chunk(a0 + d * kChunk);
+        Cols cur = load_chunk(a0);
         for (int64_t it = 0; it < nfull; ++it) {
-          const int64_t base = a0 + it * kChunk;
-          if constexpr (TOPK) make_room(sel, kChunk, L.k, lane);
+          const int64_t base = a0 + it * kC;
+          if constexpr (TOPK) make_room(sel, kC, L.k, lane);
           // the prefetch is unconditional (a conditional load would make the
-          // compiler wait for every load before evaluating q[0]); past the
+          // compiler wait for every load before evaluating cur); past the
           // last chunk it re-reads the current one, which is still cached
-          const bool more = it + kPrefetch < nfull;
-          const Cols nxt = load_chunk(more ? base + kPrefetch * kChunk : base);
-          chunk(q[0], base);
-#pragma unroll
-          for (int d = 0; d + 1 < kPrefetch; ++d) q[d] = q[d + 1];
-          q[kPrefetch - 1] = nxt;
+          const bool more = it + 1 < nfull;
+          const Cols nxt = load_chunk(more ? base + kC : base);
+          chunk(cur, base);
+          cur = nxt;
         }
-        body = a0 + nfull * kChunk;
+        body = a0 + nfull * kC;
       }
     }
-    for (int64_t base = body; base < pe; base += kChunk) masked(base, (pe - base) < kChunk ? pe : base + kChunk);
+    for (int64_t base = body; base < pe; base += 256) masked(base, (pe - base) < 256 ? pe : base + 256);
   }
 };
+
+// Per-workgroup tables: min(G_W, G_R) by (register granules, W_B), and
+// 1 / (n_cu B) for the grid-round division.  Ends with a barrier.
+__device__ void build_tables(const EvalLaunch &L, uint8_t *dyn_lds, float *tab_rcap, uint32_t *tab_mwb,
+                             uint8_t *tab_blim, int tid, int nthreads) {
+  const KArch &A = L.arch;
+  const int row = A.nw + 1;
+  uint8_t *tab_b = dyn_lds;
+  uint8_t *tab_wtot = dyn_lds + L.tab_wtot_off;
+  // waves the register file admits per register-granule count (Eq. 4 plain
+  // reading), all slots when no registers are named
+  const int slots = A.max_waves / A.simd;
+  for (int rg = tid; rg <= A.nr; rg += nthreads) {
+    int wtot = A.max_waves;
+    if (rg > 0) {
+      const int per_simd = A.vgprs / (rg * A.vgpr_gran);
+      wtot = A.simd * (per_simd < slots ? per_simd : slots);
+    }
+    tab_wtot[rg] = (uint8_t)wtot;
+  }
+  // Eq. 3 block slots, and ceil(2^16 / W_B) for exact small divisions
+  for (int wb = tid; wb <= A.nw; wb += nthreads) {
+    tab_mwb[wb] = wb > 0 ? (65536u + (uint32_t)wb - 1u) / (uint32_t)wb : 0u;
+    const int blim = (wb == 1 && A.exempt) ? 255 : (A.max_blocks < 255 ? A.max_blocks : 255);
+    tab_blim[wb] = (uint8_t)blim;
+  }
+  for (int i = tid; i <= A.max_waves; i += nthreads) tab_rcap[i] = i > 0 ? 1.0f / (float)(A.n_cu * i) : 0.0f;
+  __syncthreads();
+  // min(G_W, G_R) = min(B_lim, floor(wtot / W_B)): the register bound never
+  // exceeds floor(max_waves / W_B), the wave-slot part of Eq. 3
+  const int n_tab = (A.nr + 1) * row;
+  for (int i = tid; i < n_tab; i += nthreads) {
+    const int rg = i / row, wb = i - rg * row;
+    uint32_t b = 0;
+    if (wb >= 1) {
+      b = ((uint32_t)tab_wtot[rg] * tab_mwb[wb]) >> 16;
+      b = b < tab_blim[wb] ? b : tab_blim[wb];
+    }
+    tab_b[i] = (uint8_t)b;
+  }
+  __syncthreads();
+}
+
+// The wave-uniform record of variant v (Eq. 5 bound, Eq. 6 per-variant sum,
+// divergence weight) and its per-U / per-W_B tables in this wave's LDS.
+template <Mode MODE>
+__device__ __forceinline__ void setup_piece(const EvalLaunch &L, Piece &pc, WaveLds &wl, int64_t v, int64_t s0,
+                                            int lane) {
+  const KArch &A = L.arch;
+  pc.valid = true;
+  pc.gs = 0;
+  pc.P = 0.f;
+  pc.D = 1.f;
+  pc.s0 = s0;
+  pc.a4 = wl.a4;
+  pc.a5 = wl.a5;
+  if constexpr (MODE == Mode::Model) {
+    const int32_t nfp = L.var.n_fp[v], nint = L.var.n_int[v], nld = L.var.n_ld[v], nst = L.var.n_st[v];
+    const int32_t nbr = L.var.n_br[v], nbar = L.var.n_bar[v];
+    const int32_t nreg = L.var.n_reg ? L.var.n_reg[v] : 0;
+    const int32_t S = L.var.lds[v];
+    const float d = L.var.div[v];
+    const uint32_t cmax = 1u << 24;
+    pc.valid = (uint32_t)nfp < cmax && (uint32_t)nint < cmax && (uint32_t)nld < cmax && (uint32_t)nst < cmax &&
+               (uint32_t)nbr < cmax && (uint32_t)nreg < cmax && (uint32_t)nbar <= (1u << 14) && d >= 0.0f &&
+               d <= 1.0f;
+    // Eq. 5 with a floor; S = 0 does not limit
+    if (S == 0) {
+      pc.gs = kUnlimited;
+    } else if (S < 0 || S > A.max_lds) {
+      pc.gs = 0;
+    } else {
+      const int32_t alloc = ((S + A.lds_gran - 1) / A.lds_gran) * A.lds_gran;
+      pc.gs = A.lds_cu / alloc;
+    }
+    // Eq. 6 per-variant part, fixed binary32 order
+    const float s1f = A.cfp * (float)nfp;
+    const float s2f = A.cint * (float)nint;
+    const float s3f = A.cmem * (float)(nld + nst);
+    const float s6f = A.creg * (float)nreg;
+    float P = s1f + s2f;
+    P = P + s3f;
+    P = P + s6f;
+    pc.P = P;
+    const float A4 = A.cctrl * (float)nbr;
+    pc.D = 1.0f + d;
+    // branch term per U, barrier term per W_B
+    wave_lds_sync();
+    if (lane < A.max_unroll) wl.a4[lane] = A4 / (float)(lane + 1);
+    if (lane < A.nw) wl.a5[lane + 1] = A.csync * (float)(nbar * (lane + 1));
+    wave_lds_sync();
+  }
+}
 
 template <Mode MODE, bool HAS_GRID, bool TOPK>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SA_WAVES_PER_EU)))
@@ -492,44 +609,9 @@ void sa_eval_kernel(EvalLaunch L) {
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = tid / kWaveSize;
-  const int row = A.nw + 1;
-  uint8_t *tab_b = dyn_lds;
-  uint8_t *tab_wtot = dyn_lds + L.tab_wtot_off;
-
-  if constexpr (MODE == Mode::Model) {
-    // waves the register file admits per register-granule count (Eq. 4 plain
-    // reading), all slots when no registers are named
-    const int slots = A.max_waves / A.simd;
-    for (int rg = tid; rg <= A.nr; rg += kBlockThreads) {
-      int wtot = A.max_waves;
-      if (rg > 0) {
-        const int per_simd = A.vgprs / (rg * A.vgpr_gran);
-        wtot = A.simd * (per_simd < slots ? per_simd : slots);
-      }
-      tab_wtot[rg] = (uint8_t)wtot;
-    }
-    // Eq. 3 block slots, and ceil(2^16 / W_B) for exact small divisions
-    for (int wb = tid; wb <= A.nw; wb += kBlockThreads) {
-      tab_mwb[wb] = wb > 0 ? (65536u + (uint32_t)wb - 1u) / (uint32_t)wb : 0u;
-      const int blim = (wb == 1 && A.exempt) ? 255 : (A.max_blocks < 255 ? A.max_blocks : 255);
-      tab_blim[wb] = (uint8_t)blim;
-    }
-    for (int i = tid; i <= A.max_waves; i += kBlockThreads) tab_rcap[i] = i > 0 ? 1.0f / (float)(A.n_cu * i) : 0.0f;
-    __syncthreads();
-    // min(G_W, G_R) = min(B_lim, floor(wtot / W_B)): the register bound never
-    // exceeds floor(max_waves / W_B), the wave-slot part of Eq. 3
-    const int n_tab = (A.nr + 1) * row;
-    for (int i = tid; i < n_tab; i += kBlockThreads) {
-      const int rg = i / row, wb = i - rg * row;
-      uint32_t b = 0;
-      if (wb >= 1) {
-        b = ((uint32_t)tab_wtot[rg] * tab_mwb[wb]) >> 16;
-        b = b < tab_blim[wb] ? b : tab_blim[wb];
-      }
-      tab_b[i] = (uint8_t)b;
-    }
-  }
-  __syncthreads();  // waves are independent below
+  (void)A;
+  if constexpr (MODE == Mode::Model) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, kBlockThreads);
+  const uint8_t *tab_b = dyn_lds;
 
   const int64_t wt = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (wt >= L.n_tiles) return;
@@ -555,55 +637,13 @@ void sa_eval_kernel(EvalLaunch L) {
     if (pe <= e) continue;
 
     Piece pc;
-    pc.valid = true;
-    pc.gs = 0;
-    pc.P = 0.f;
-    pc.D = 1.f;
-    pc.s0 = s0;
-    pc.a4 = wl[w].a4;
-    pc.a5 = wl[w].a5;
-    if constexpr (MODE == Mode::Model) {
-      const int32_t nfp = L.var.n_fp[v], nint = L.var.n_int[v], nld = L.var.n_ld[v], nst = L.var.n_st[v];
-      const int32_t nbr = L.var.n_br[v], nbar = L.var.n_bar[v];
-      const int32_t nreg = L.var.n_reg ? L.var.n_reg[v] : 0;
-      const int32_t S = L.var.lds[v];
-      const float d = L.var.div[v];
-      const uint32_t cmax = 1u << 24;
-      pc.valid = (uint32_t)nfp < cmax && (uint32_t)nint < cmax && (uint32_t)nld < cmax && (uint32_t)nst < cmax &&
-                 (uint32_t)nbr < cmax && (uint32_t)nreg < cmax && (uint32_t)nbar <= (1u << 14) && d >= 0.0f &&
-                 d <= 1.0f;
-      // Eq. 5 with a floor; S = 0 does not limit
-      if (S == 0) {
-        pc.gs = kUnlimited;
-      } else if (S < 0 || S > A.max_lds) {
-        pc.gs = 0;
-      } else {
-        const int32_t alloc = ((S + A.lds_gran - 1) / A.lds_gran) * A.lds_gran;
-        pc.gs = A.lds_cu / alloc;
-      }
-      // Eq. 6 per-variant part, fixed binary32 order
-      const float s1f = A.cfp * (float)nfp;
-      const float s2f = A.cint * (float)nint;
-      const float s3f = A.cmem * (float)(nld + nst);
-      const float s6f = A.creg * (float)nreg;
-      float P = s1f + s2f;
-      P = P + s3f;
-      P = P + s6f;
-      pc.P = P;
-      const float A4 = A.cctrl * (float)nbr;
-      pc.D = 1.0f + d;
-      // per-wave tables of the variant: branch term per U, barrier term per W_B
-      wave_lds_sync();
-      if (lane < A.max_unroll) wl[w].a4[lane] = A4 / (float)(lane + 1);
-      if (lane < A.nw) wl[w].a5[lane + 1] = A.csync * (float)(nbar * (lane + 1));
-      wave_lds_sync();
-    }
+    setup_piece<MODE>(L, pc, wl[w], v, s0, lane);
 
     if constexpr (TOPK) {
       sel.count = 0;
       sel.theta = kThetaInit;
     }
-    Evaluator<MODE, HAS_GRID, TOPK> ev{L, tb, pc, sel, lane};
+    Evaluator<MODE, HAS_GRID, TOPK, 4> ev{L, tb, pc, sel, lane};
     ev.run(e, pe);
 
     if constexpr (TOPK) {
@@ -667,6 +707,166 @@ __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
   }
 }
 
+// ---------------------------------------------------------------- planned batches
+
+// Persistent kernel over a plan's workgroup items (static stride over the
+// grid).  kind 0 items: each wave evaluates whole segments and writes their
+// rows.  kind 1 items: each wave selects over its part of one segment, the
+// parts meet in LDS and wave 0 writes the row (or the item's fragment).
+template <Mode MODE, bool HAS_GRID, bool TOPK, int ITEMS, int WPB>
+__global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev P) {
+  extern __shared__ __align__(16) uint8_t dyn_lds[];
+  __shared__ float tab_rcap[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 1];
+  __shared__ uint8_t tab_blim[kMaxWB + 1];
+  __shared__ WaveLds wl[WPB];
+  __shared__ uint64_t wgk[WPB][SA_K_MAX];
+
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int w = tid / kWaveSize;
+  if constexpr (MODE == Mode::Model) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, 64 * WPB);
+  const Tables tb{dyn_lds, tab_rcap};
+  const int64_t n_evals = L.n_evals;
+  const int64_t *seg = L.cfg.seg;
+  const int k = L.k;
+  Selector sel;
+  sel.buf = wl[w].cand;
+  sel.count = 0;
+  sel.theta = kThetaInit;
+
+  for (int64_t item = blockIdx.x; item < P.n_items; item += gridDim.x) {
+    const PlanItem it = P.items[item];
+    const PlanWave pw = P.waves[item * WPB + w];
+    if (it.kind == 0) {
+      const int64_t v1 = pw.v1 < L.n_var ? pw.v1 : L.n_var;
+      for (int64_t v = pw.v0 > 0 ? pw.v0 : 0; v < v1; ++v) {
+        const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
+        const int64_t s1 = uniform64(clamp_off(seg[v + 1], n_evals));
+        if (s1 <= s0) {
+          if constexpr (TOPK) write_final(kKeyNone, k, lane, v, L.topk_idx, L.topk_val, nullptr, 0);
+          continue;
+        }
+        Piece pc;
+        setup_piece<MODE>(L, pc, wl[w], v, s0, lane);
+        sel.count = 0;
+        sel.theta = kThetaInit;
+        Evaluator<MODE, HAS_GRID, TOPK, ITEMS> ev{L, tb, pc, sel, lane};
+        ev.run(s0, s1);
+        if constexpr (TOPK) {
+          const uint64_t mine = select_k(sel, k, lane);
+          write_final(mine, k, lane, v, L.topk_idx, L.topk_val, MODE == Mode::Keys ? L.keys : nullptr, s0);
+        }
+      }
+    } else {
+      const int64_t v = it.v < L.n_var ? (it.v > 0 ? it.v : 0) : L.n_var - 1;
+      const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
+      const int64_t s1 = uniform64(clamp_off(seg[v + 1], n_evals));
+      int64_t e0 = pw.e0 > s0 ? pw.e0 : s0;
+      int64_t e1 = pw.e1 < s1 ? pw.e1 : s1;
+      uint64_t mine = kKeyNone;
+      if (e1 > e0) {
+        Piece pc;
+        setup_piece<MODE>(L, pc, wl[w], v, s0, lane);
+        sel.count = 0;
+        sel.theta = kThetaInit;
+        Evaluator<MODE, HAS_GRID, TOPK, ITEMS> ev{L, tb, pc, sel, lane};
+        ev.run(e0, e1);
+        if constexpr (TOPK) mine = select_k(sel, k, lane);
+      }
+      if constexpr (TOPK) {
+        if (lane < k) wgk[w][lane] = mine;
+      }
+    }
+    if constexpr (TOPK) {
+      __syncthreads();
+      if (it.kind == 1 && w == 0) {
+        const int64_t v = it.v < L.n_var ? (it.v > 0 ? it.v : 0) : L.n_var - 1;
+        const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
+        sel.count = 0;
+        sel.theta = kThetaInit;
+        for (int base = 0; base < WPB * k; base += 64) {
+          const int j = base + lane;
+          const uint64_t key = j < WPB * k ? wgk[j / k][j % k] : kKeyNone;
+          make_room(sel, 64, k, lane);
+          const bool cand[1] = {key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta};
+          const uint64_t keys1[1] = {key};
+          offer<1>(sel, cand, keys1);
+        }
+        const uint64_t m = select_k(sel, k, lane);
+        if (it.slot < 0) {
+          write_final(m, k, lane, v, L.topk_idx, L.topk_val, MODE == Mode::Keys ? L.keys : nullptr, s0);
+        } else if (lane < k) {
+          L.frag[(int64_t)it.slot * k + lane] = m;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Combine the fragments of segments a plan split over several workgroup
+// items.  One wave per split record.
+__global__ __launch_bounds__(kBlockThreads) void sa_split_merge_kernel(EvalLaunch L, PlanDev P) {
+  __shared__ uint64_t cand[kWavesPerBlock][kCandCap];
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWaveSize;
+  const int k = L.k;
+  Selector sel;
+  sel.buf = cand[w];
+  for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + w; i < P.n_splits; i += (int64_t)gridDim.x * kWavesPerBlock) {
+    const PlanSplit sp = P.splits[i];
+    const int64_t v = sp.v;
+    if (v < 0 || v >= L.n_var) continue;
+    const int64_t s0 = uniform64(clamp_off(L.cfg.seg[v], L.n_evals));
+    sel.count = 0;
+    sel.theta = kThetaInit;
+    const int64_t n_keys = sp.n_slots * k;
+    for (int64_t base = 0; base < n_keys; base += 64) {
+      const int64_t j = base + lane;
+      const uint64_t key = j < n_keys ? L.frag[sp.first_slot * k + j] : kKeyNone;
+      make_room(sel, 64, k, lane);
+      const bool c[1] = {key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta};
+      const uint64_t keys1[1] = {key};
+      offer<1>(sel, c, keys1);
+    }
+    const uint64_t mine = select_k(sel, k, lane);
+    write_final(mine, k, lane, v, L.topk_idx, L.topk_val, L.keys, s0);
+  }
+}
+
+template <Mode M, bool G, bool K, int I, int WPB>
+hipError_t launch_plan_one(const EvalLaunch &L, const PlanDev &P, int n_cu, hipStream_t stream) {
+  if (P.n_items == 0) return hipSuccess;
+  const size_t dyn = M == Mode::Model ? (size_t)L.dyn_lds_bytes : 0;
+  static thread_local int resident = -1;  // workgroups per CU for this instantiation
+  static thread_local size_t resident_dyn = (size_t)-1;
+  if (resident < 0 || resident_dyn != dyn) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sa_plan_kernel<M, G, K, I, WPB>, 64 * WPB, dyn) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    resident = nb;
+    resident_dyn = dyn;
+  }
+  int64_t grid = (int64_t)resident * n_cu;
+  if (grid > P.n_items) grid = P.n_items;
+  hipLaunchKernelGGL((sa_plan_kernel<M, G, K, I, WPB>), dim3((uint32_t)grid), dim3(64 * WPB), dyn, stream, L, P);
+  return hipGetLastError();
+}
+
+template <Mode M, bool G, bool K>
+hipError_t launch_plan_shape(const EvalLaunch &L, const PlanDev &P, const PlanShape &S, int n_cu, hipStream_t stream) {
+#define SA_SHAPE(I, W) \
+  if (S.items == I && S.wpb == W) return launch_plan_one<M, G, K, I, W>(L, P, n_cu, stream);
+  SA_SHAPE(1, 4) SA_SHAPE(2, 4) SA_SHAPE(4, 4)
+  SA_SHAPE(1, 8) SA_SHAPE(2, 8) SA_SHAPE(4, 8)
+  SA_SHAPE(1, 16) SA_SHAPE(2, 16) SA_SHAPE(4, 16)
+#undef SA_SHAPE
+  return hipErrorInvalidValue;
+}
+
 template <Mode M, bool G, bool K>
 hipError_t launch_one(const EvalLaunch &L, hipStream_t stream) {
   const int64_t blocks = (L.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -686,6 +886,27 @@ hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk,
     return topk ? launch_one<Mode::Model, true, true>(L, stream) : launch_one<Mode::Model, true, false>(L, stream);
   }
   return topk ? launch_one<Mode::Model, false, true>(L, stream) : launch_one<Mode::Model, false, false>(L, stream);
+}
+
+hipError_t launch_plan(const EvalLaunch &L, const PlanDev &P, const PlanShape &S, Mode mode, bool has_grid, bool topk,
+                       int n_cu, hipStream_t stream) {
+  if (mode == Mode::Keys) {
+    return topk ? launch_plan_shape<Mode::Keys, false, true>(L, P, S, n_cu, stream) : hipErrorInvalidValue;
+  }
+  if (has_grid) {
+    return topk ? launch_plan_shape<Mode::Model, true, true>(L, P, S, n_cu, stream)
+                : launch_plan_shape<Mode::Model, true, false>(L, P, S, n_cu, stream);
+  }
+  return topk ? launch_plan_shape<Mode::Model, false, true>(L, P, S, n_cu, stream)
+              : launch_plan_shape<Mode::Model, false, false>(L, P, S, n_cu, stream);
+}
+
+hipError_t launch_split_merge(const EvalLaunch &L, const PlanDev &P, hipStream_t stream) {
+  if (P.n_splits == 0) return hipSuccess;
+  int64_t blocks = (P.n_splits + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(sa_split_merge_kernel, dim3((uint32_t)blocks), dim3(kBlockThreads), 0, stream, L, P);
+  return hipGetLastError();
 }
 
 hipError_t launch_merge(const EvalLaunch &L, hipStream_t stream) {

@@ -65,7 +65,43 @@ struct EvalLaunch {
 
 enum class Mode { Model, Keys };
 
+// A plan cuts a CSR batch into workgroup items.  kind 0: whole segments
+// [v0, v1) per wave.  kind 1: one segment's range split into one part per
+// wave, merged in LDS; `slot` < 0 means the item covers the whole segment,
+// else its k keys go to fragment slot `slot` and a split record names the
+// slots to combine.
+struct PlanItem {
+  int32_t kind;
+  int32_t slot;
+  int64_t v;
+};
+struct PlanWave {
+  int64_t e0, e1;  // kind 1: evaluation range of this wave's part
+  int64_t v0, v1;  // kind 0: segments of this wave
+};
+struct PlanSplit {
+  int64_t v;
+  int64_t first_slot;
+  int64_t n_slots;
+  int64_t pad;
+};
+struct PlanDev {
+  const PlanItem *items;
+  const PlanWave *waves;   // n_items x wpb
+  const PlanSplit *splits;
+  int64_t n_items, n_splits;
+};
+
+// Launch shape of a plan: evaluations per wave part, items per lane (1, 2,
+// 4: 16-, 8- or 4-byte loads), waves per workgroup (4, 8, 16).
+struct PlanShape {
+  int32_t tile, items, wpb;
+};
+
 hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream);
+hipError_t launch_plan(const EvalLaunch &L, const PlanDev &P, const PlanShape &S, Mode mode, bool has_grid, bool topk,
+                       int n_cu, hipStream_t stream);
+hipError_t launch_split_merge(const EvalLaunch &L, const PlanDev &P, hipStream_t stream);
 hipError_t launch_merge(const EvalLaunch &L, hipStream_t stream);
 
 }  // namespace sa

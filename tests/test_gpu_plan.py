@@ -1,0 +1,164 @@
+"""GPU parity of planned batches (persistent kernel over workgroup items,
+split-segment merge, graph capture, autotuner) against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_08547_amd import api, workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def say(*a):
+    print("[gpu-plan]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def check(ref, got, rows=None):
+    if got.get("occ") is not None:
+        assert np.array_equal(ref["occ"], got["occ"])
+    if got.get("score") is not None:
+        assert np.array_equal(ref["score32"].view(np.uint32), got["score"].view(np.uint32))
+    ridx, rval = ref["idx"], ref["val"]
+    gidx, gval = got["idx"], got["val"]
+    if rows is not None:
+        gidx, gval = gidx[rows], gval[rows]
+    assert np.array_equal(ridx, gidx), np.flatnonzero((ridx != gidx).any(1))[:10]
+    assert np.array_equal(rval.view(np.uint32), gval.view(np.uint32))
+
+
+def run_plan(batch, k, shape, arch=None, **kw):
+    a = arch or oracle.arch_cdna4()
+    var, cfg = api.device_batch(batch)
+    plan = api.Plan(batch.seg, k=k, shape=shape)
+    say("plan", batch.name, "shape", plan.shape, "items", plan.n_items, "splits", plan.n_splits)
+    out = plan.score(a, var, cfg, **kw)
+    torch.cuda.synchronize()
+    return {key: (None if t is None else t.cpu().numpy()) for key, t in out.items()}
+
+
+SIZES = [0, 1, 5, 63, 64, 65, 255, 256, 257, 1000, 4095, 4096, 4097, 10000, 0, 3, 20000, 1, 70000, 0]
+
+
+@pytest.mark.parametrize("items", [1, 2, 4])
+@pytest.mark.parametrize("wpb", [4, 8, 16])
+def test_plan_shapes_ragged(items, wpb):
+    b = workloads.custom_batch(40 + items * wpb, SIZES, with_grid=True, name="plan-ragged")
+    ref = oracle.run(oracle.arch_cdna4(), b.variants, b.configs(), k=8)
+    check(ref, run_plan(b, 8, (1024, items, wpb)))
+
+
+@pytest.mark.parametrize("tile", [256, 2048, 8192])
+def test_plan_tiles_and_no_grid(tile):
+    b = workloads.custom_batch(50 + tile, SIZES, with_grid=False, name="plan-nogrid")
+    ref = oracle.run(oracle.arch_cdna4(), b.variants, b.configs(), k=16)
+    check(ref, run_plan(b, 16, (tile, 4, 4)))
+
+
+def test_plan_optional_outputs_and_occupancy_only():
+    b = workloads.custom_batch(61, SIZES, with_grid=True, name="plan-outputs")
+    ref = oracle.run(oracle.arch_cdna4(), b.variants, b.configs(), k=8)
+    got = run_plan(b, 8, (1024, 4, 8), want_score=False, want_occ=False)
+    assert np.array_equal(ref["idx"], got["idx"])
+    got = run_plan(b, 8, (1024, 4, 8), want_topk=False)
+    assert np.array_equal(ref["occ"], got["occ"])
+    assert np.array_equal(ref["score32"].view(np.uint32), got["score"].view(np.uint32))
+
+
+def test_plan_topk_keys():
+    g = np.random.default_rng(23)
+    sizes = np.array(SIZES + [50000], np.int64)
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(seg[-1])
+    keys = (g.standard_normal(n) * 10).astype(np.float32)
+    keys[g.random(n) < 0.05] = np.inf
+    keys[g.random(n) < 0.02] = np.nan
+    keys[g.random(n) < 0.2] = np.float32(0.5)
+    ridx, rval = oracle.topk(keys, seg, 8)
+    plan = api.Plan(seg, k=8, shape=(1024, 2, 4))
+    idx, val = plan.topk(torch.from_numpy(keys).cuda(), torch.from_numpy(seg).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(ridx, idx.cpu().numpy())
+    assert np.array_equal(rval.view(np.uint32), val.cpu().numpy().view(np.uint32))
+
+
+def test_plan_c1_full():
+    b = workloads.c1()
+    ref = oracle.run(oracle.arch_cdna4(), b.variants, b.configs(), k=8)
+    check(ref, run_plan(b, 8, (4096, 4, 4)))
+
+
+def test_plan_graph_capture_replays():
+    """sa_plan_score captured in a HIP graph: every replay equals the eager
+    result (eager work and synchronisation between replays)."""
+    b = workloads.custom_batch(71, SIZES, with_grid=True, name="plan-graph")
+    a = oracle.arch_cdna4()
+    var, cfg = api.device_batch(b)
+    plan = api.Plan(b.seg, k=8, shape=(1024, 4, 4))
+    ws = api.Workspace(plan.workspace_bytes, "cuda")
+    eager = plan.score(a, var, cfg, workspace=ws)
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in eager.items()}
+    outs = {k: torch.empty_like(v) for k, v in eager.items()}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.score(a, var, cfg, outputs=outs, workspace=ws)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.score(a, var, cfg, outputs=outs, workspace=ws)
+    for r in range(3):
+        for t in outs.values():
+            t.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for key in eager:
+            assert torch.equal(eager[key].view(torch.int32), outs[key].view(torch.int32)), (r, key)
+
+
+def test_autotuner_picks_a_valid_shape():
+    b = workloads.custom_batch(81, [5000, 64, 300000, 7, 20000, 0], with_grid=True, name="plan-tune")
+    a = oracle.arch_cdna4()
+    var, cfg = api.device_batch(b)
+    shape, ms = api.autotune(a, var, cfg, k=8, reps=2)
+    say("autotuned", shape, ms)
+    assert shape[0] in (1024, 2048, 4096, 8192) and shape[1] in (1, 2, 4) and shape[2] in (4, 8, 16)
+    assert 0 < ms < 1000
+    ref = oracle.run(a, b.variants, b.configs(), k=8)
+    check(ref, run_plan(b, 8, shape))
+
+
+def test_plan_c2_sampled():
+    """10,000 variants with log-uniform search spaces in [64, 262,144]
+    (about 3e8 evaluations), top-16, one planned launch; 200 variants
+    (and the five longest) recomputed by the oracle one by one."""
+    b = workloads.c2()
+    say("c2 evaluations", b.n_evals)
+    a = oracle.arch_cdna4()
+    var, cfg = api.device_batch(b)
+    plan = api.Plan(b.seg, k=16, shape=(4096, 4, 4))
+    out = plan.score(a, var, cfg, want_score=False, want_occ=False)
+    torch.cuda.synchronize()
+    idx, val = out["idx"].cpu().numpy(), out["val"].cpu().numpy()
+    g = np.random.default_rng(5)
+    sizes = np.diff(b.seg)
+    rows = np.unique(np.concatenate([g.choice(b.n_var, 200, replace=False), np.argsort(sizes)[-5:]]))
+    sub_sizes = sizes[rows]
+    sub_seg = np.concatenate([[0], np.cumsum(sub_sizes)]).astype(np.int64)
+    take = np.concatenate([np.arange(b.seg[r], b.seg[r + 1]) for r in rows])
+    sub_var = {f: v[rows] for f, v in b.variants.items()}
+    sub_cfg = dict(seg=sub_seg, block=b.block[take], unroll=b.unroll[take], regs=b.regs[take], grid=b.grid[take])
+    ref = oracle.run(a, sub_var, sub_cfg, k=16, want_occ=False, want_f64=False)
+    assert np.array_equal(ref["idx"], idx[rows])
+    assert np.array_equal(ref["val"].view(np.uint32), val[rows].view(np.uint32))
+    del var, cfg
+    torch.cuda.empty_cache()
