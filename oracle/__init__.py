@@ -130,6 +130,8 @@ def lib():
             L.oracle_topk.restype = ctypes.c_int
             L.oracle_run.argtypes = [P(OracleArch)] + [vp] * 14 + [i64, vp, vp, vp, i32, vp, vp, i32]
             L.oracle_run.restype = ctypes.c_int
+            L.oracle_terms.argtypes = [P(OracleArch)] + [i32] * 8 + [f32, i64, vp, vp, vp, vp, vp]
+            L.oracle_terms.restype = None
             L.oracle_max_threads.argtypes = []
             L.oracle_max_threads.restype = ctypes.c_int
             _lib = L
@@ -242,3 +244,27 @@ def topk(keys, seg, k: int, nthreads: int | None = None):
     if rc != 0:
         raise MemoryError("oracle_topk failed to allocate scratch")
     return idx, val
+
+
+TERM_NAMES = ("W_B", "G_W", "G_R", "G_S", "B", "W", "Eprime", "F", "score")
+
+
+def terms(arch: dict, v: dict, T, U, R, G=None) -> dict:
+    """Binary64 per-configuration terms of one variant (arrays)."""
+    a = _to_struct(arch)
+    T, U, R = (_c(x, np.int32) for x in (T, U, R))
+    Gc = None if G is None else _c(G, np.int32)
+    n = T.shape[0]
+    out = np.empty((n, 9), np.float64)
+    lib().oracle_terms(ctypes.byref(a), int(v["n_fp"]), int(v["n_int"]), int(v["n_ld"]), int(v["n_st"]),
+                       int(v["n_br"]), int(v["n_bar"]), int(v.get("n_reg", 0)), int(v["lds"]),
+                       float(np.float32(v["div"])), n, _ptr(T), _ptr(U), _ptr(R), _ptr(Gc), _ptr(out))
+    return {k: out[:, i] for i, k in enumerate(TERM_NAMES)}
+
+
+def features(arch: dict, v: dict, T, U, R, G=None) -> np.ndarray:
+    """The learned correction's 24 binary32 features (see oracle/mlp.py)."""
+    from . import mlp
+
+    t = terms(arch, v, T, U, R, G)
+    return mlp.features_from_terms(v, T, U, R, G, arch["n_cu"], t)

@@ -356,3 +356,43 @@ int oracle_max_threads(void) {
   return 1;
 #endif
 }
+
+/* Per-configuration terms of the model, binary64, for the learned
+ * correction's features: out[9 i + 0..8] = W_B, G_W, G_R, G_S, B*, W*, E', F,
+ * score (E', F and score are +inf / 0 for illegal configurations; unbounded
+ * G_R / G_S are reported as 2^40).  `G` may be NULL. */
+void oracle_terms(const oracle_arch *a, int32_t n_fp, int32_t n_int, int32_t n_ld, int32_t n_st, int32_t n_br,
+                  int32_t n_bar, int32_t n_reg, int32_t S, float d, int64_t n, const int32_t *T,
+                  const int32_t *U, const int32_t *R, const int32_t *G, double *out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double *o = out + 9 * i;
+    const int32_t *g = G ? &G[i] : NULL;
+    int64_t W_B = or_ceil_div(T[i] > 0 ? T[i] : 1, a->wave_size);
+    o[0] = (double)W_B;
+    o[1] = (double)or_G_W(a, W_B);
+    o[2] = (double)(R[i] >= 0 ? or_G_R(a, R[i], W_B) : 0);
+    o[3] = (double)(S >= 0 ? or_G_S(a, S) : 0);
+    int64_t Wb2;
+    int valid = or_variant_valid(n_fp, n_int, n_ld, n_st, n_br, n_bar, n_reg, d) && or_config_legal(a, U[i], g);
+    int64_t B = valid ? or_active_blocks(a, T[i], R[i], S, &Wb2) : 0;
+    o[4] = (double)B;
+    o[5] = (double)(B * W_B);
+    if (B == 0) {
+      o[6] = INFINITY;
+      o[7] = 0.0;
+      o[8] = INFINITY;
+      continue;
+    }
+    double O_fl = (double)a->cpi_fp * n_fp + (double)a->cpi_int * n_int;
+    double O_mem = (double)a->cpi_mem * ((double)n_ld + (double)n_st);
+    double O_ctrl = (double)a->cpi_ctrl * n_br / U[i] + (double)a->cpi_sync * ((double)n_bar * W_B);
+    double O_reg = (double)a->cpi_reg * n_reg;
+    double E = (O_fl + O_mem + O_ctrl + O_reg) * (1.0 + (double)d);
+    int64_t num, den;
+    or_F_terms(a, B, W_B, U[i], g, &num, &den);
+    double F = (double)num / (double)den;
+    o[6] = E;
+    o[7] = F;
+    o[8] = E * F;
+  }
+}

@@ -1,0 +1,104 @@
+"""Pins of the learned correction's binary64 oracle: backward pass against
+central finite differences, GELU and bfloat16 rounding against their
+definitions, features against the hand-worked case, Adam and the ranking
+metrics against textbook values and scipy."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+
+
+def test_bf16_rounding_known_values():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -2.5, 3.1415927, 0.0, 65504.0], np.float32)
+    got = mlp.bf16(vals)
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: even mantissa -> 1.0;
+    # 1 + 3 * 2^-8 is a tie between 1 + 2^-7 and 1 + 2^-6: even -> 1 + 2^-6
+    want = [1.0, 1.0, 1.0 + 2 ** -6, 1.0, -2.5, 3.140625, 0.0, 65536.0]
+    assert got.tolist() == want
+
+
+def test_gelu_definition():
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    a = np.linspace(-6, 6, 121)
+    num = (mlp.gelu(a + 1e-6) - mlp.gelu(a - 1e-6)) / 2e-6
+    assert np.max(np.abs(num - mlp.gelu_grad(a))) < 1e-8
+    # Phi(1) = 0.841344746...
+    assert abs(mlp.gelu(np.array([1.0]))[0] - 0.8413447460685429) < 1e-15
+
+
+def test_backward_matches_finite_differences():
+    g = np.random.default_rng(0)
+    p = mlp.init_params(seed=3, hidden=8)
+    p = {k: v.astype(np.float64) for k, v in p.items()}
+    p["W1"][:, 24:] = 0.0
+    x = g.standard_normal((16, 32))
+    x[:, 24:] = 0.0
+    r = g.standard_normal(16)
+    loss, grads, _ = mlp.loss_and_grads(p, x, r, quantise=False)
+    eps = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "w3", "b3"):
+        flat = p[name].reshape(-1)
+        num = np.zeros_like(flat)
+        for i in range(flat.size):
+            old = flat[i]
+            flat[i] = old + eps
+            lp, _, _ = mlp.loss_and_grads(p, x, r, quantise=False)
+            flat[i] = old - eps
+            lm, _, _ = mlp.loss_and_grads(p, x, r, quantise=False)
+            flat[i] = old
+            num[i] = (lp - lm) / (2 * eps)
+        ana = np.asarray(grads[name]).reshape(-1)
+        scale = max(1e-12, np.max(np.abs(num)))
+        assert np.max(np.abs(num - ana)) / scale <= 1e-6, name
+
+
+def test_features_of_the_hand_worked_case():
+    a = oracle.arch_cdna4()
+    v = dict(n_fp=200, n_int=150, n_ld=40, n_st=10, n_br=12, n_bar=2, n_reg=0, lds=0, div=0.25)
+    f = oracle.features(a, v, [256], [4], [128], [512])[0]
+    names = dict(zip(mlp.FEATURES, f))
+    assert names["ln1p_n_fp"] == np.float32(math.log(201))
+    assert names["log2T_10"] == np.float32(0.8)
+    assert names["U_minus1_7"] == np.float32(3 / 7)
+    assert names["WB_16"] == np.float32(0.25)
+    assert names["GR_32"] == np.float32(4 / 32)  # 4 waves per SIMD x 4 SIMDs / 4 waves per block
+    assert names["W_32"] == np.float32(16 / 32)
+    assert names["ln_score"] == np.float32(math.log(23.203125))
+    assert names["inv_F"] == np.float32(0.5)
+    assert names["log2_G_ncu_3"] == np.float32(1 / 3)
+    assert names["intensity_gt_4"] == 0.0 and names["ln1p_intensity"] == np.float32(math.log(5.0))
+
+
+def test_adam_first_step_is_sign_of_gradient_times_lr():
+    p = {"w": np.array([1.0, -2.0, 0.5], np.float32)}
+    g = {"w": np.array([0.3, -4.0, 1e-3])}
+    out = mlp.adam_step(p, g, {}, lr=1e-3)
+    # bias-corrected first step: m_hat = g, v_hat = g^2 -> update lr * g / (|g| + eps)
+    want = p["w"] - 1e-3 * g["w"] / (np.abs(g["w"]) + 1e-8)
+    assert np.allclose(out["w"], want.astype(np.float32), rtol=0, atol=1e-7)
+
+
+def test_ranking_metrics():
+    scipy_stats = pytest.importorskip("scipy.stats")
+    g = np.random.default_rng(1)
+    for _ in range(20):
+        a = g.integers(0, 10, 50).astype(float)
+        b = a + g.standard_normal(50)
+        assert abs(mlp.spearman(a, b) - scipy_stats.spearmanr(a, b).correlation) < 1e-12
+    t = np.array([3.0, 1.0, 2.0])
+    assert mlp.top1_regret(np.array([0.5, 0.1, 0.2]), t) == 0.0
+    assert mlp.top1_regret(np.array([0.1, 0.5, 0.2]), t) == 2.0
+    assert mlp.top1_regret(np.array([0.1, 0.5, 0.1]), t) == 2.0  # tie -> lower index
+
+
+def test_quantised_forward_uses_bf16_weights_and_activations():
+    p = mlp.init_params(seed=1)
+    g = np.random.default_rng(2)
+    x = mlp.bf16(g.standard_normal((4, 32)))
+    fw = mlp.forward(p, x)
+    assert np.array_equal(fw["h1"], mlp.bf16(fw["h1"]))
+    assert np.array_equal(fw["W2"], mlp.bf16(p["W2"]))
+    assert fw["delta"].shape == (4,)
