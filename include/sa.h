@@ -149,8 +149,37 @@ typedef struct sa_configs {
   const int32_t *grid;   /* G: blocks in the grid (NULL = no grid dimension)  */
 } sa_configs;
 
-/* Learned correction (declared for the corrected scoring mode). */
-typedef struct sa_mlp sa_mlp;
+/*
+ * Learned correction: a 24 -> 128 -> 128 -> 1 perceptron (GELU, bfloat16
+ * weights and activations, fp32 accumulation on MFMA) that predicts, from
+ * 24 static features of one (variant, configuration), the residual Delta of
+ * the log-runtime the plain score misses; the corrected key is
+ * ln(score) + Delta.  The paper motivates learned models over static
+ * features (Sec. V, Sec. VII) without specifying one.
+ *
+ * Features (binary32, in this order): ln(1+n_fp), ln(1+n_int), ln(1+n_ld),
+ * ln(1+n_st), ln(1+n_br), n_bar/4, ln(1+n_reg), S/65536, d, log2(T)/10,
+ * (U-1)/7, R/512, log2(G/n_cu)/3 (0 without grid), W_B/16, min(G_W,32)/32,
+ * min(G_R,32)/32, min(G_S,32)/32, Bstar/32, Wstar/32, ln(1+intensity), ln E',
+ * 1/F, ln score, [intensity > 4]; intensity = n_fp / max(1, n_ld + n_st).
+ * The network input is bf16((f - feat_mean) * feat_inv_std), padded with
+ * eight zeros; h1 = bf16(GELU(W1 x + b1)), h2 = bf16(GELU(W2 h1 + b2)),
+ * Delta = w3 . h2 + b3, GELU(a) = a/2 (1 + erf(a / sqrt 2)).
+ */
+typedef struct sa_mlp {
+  const uint16_t *W1;         /* bf16 [128][32]; columns 24..31 must be zero */
+  const uint16_t *W2;         /* bf16 [128][128]                              */
+  const uint16_t *w3;         /* bf16 [128]                                   */
+  const float *b1, *b2, *b3;  /* [128], [128], [1]                            */
+  const float *feat_mean;     /* [24]                                         */
+  const float *feat_inv_std;  /* [24]                                         */
+} sa_mlp;
+
+/* Flat fp32 parameter vector used by training (master weights, Adam
+ * moments, gradients): W1 [128][32] | b1 | W2 [128][128] | b2 | w3 | b3,
+ * then one slot holding the mean squared error, padded. */
+#define SA_MLP_PARAMS 20865
+#define SA_MLP_FLAT 20992
 
 /* Human-readable name of a status code (static storage). */
 const char *sa_status_string(sa_status status);
@@ -203,7 +232,9 @@ sa_status sa_occupancy(const sa_arch *arch, const sa_variants *variants, const s
  *             order; -1 past the number of legal configurations.
  *   topk_val  float[n_variants * k] or NULL: the matching scores (+inf pad).
  *   k         1 .. 64 when topk_idx or topk_val is given, else ignored.
- *   mlp       must be NULL (plain static model).
+ *   mlp       NULL for the plain model; not yet accepted here (returns
+ *             SA_ERR_UNSUPPORTED): the corrected key is available through
+ *             sa_features + sa_surrogate_fwd.
  *   workspace device buffer of sa_workspace_bytes(...) bytes (may be NULL
  *             when no top-k is asked for).  Contents need no initialisation.
  *             Segments that span several wave-tiles leave per-tile partial
@@ -224,6 +255,27 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
  */
 sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int64_t n_evals, int32_t k,
                   int32_t *idx, float *val, void *workspace, size_t workspace_bytes, void *stream);
+
+/* The 24 features of every evaluation, feat float[n_evals][24] (features of
+ * illegal evaluations are unspecified).  Asynchronous on `stream`. */
+sa_status sa_features(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
+                      int64_t n_variants, int64_t n_evals, float *feat, void *stream);
+
+/* Delta for n rows of features (float[n][24]); delta float[n]. */
+sa_status sa_surrogate_fwd(const sa_mlp *mlp, const float *feat, int64_t n, float *delta, void *stream);
+
+/* One training step on a batch of n rows: forward, mean squared error
+ * against target float[n], backward (MFMA contractions for dW1 and dW2,
+ * per-slab partials summed in a fixed order), and Adam (lr, beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias correction for step `step` >= 1) on
+ * master / adam_m / adam_v (float[SA_MLP_FLAT] each); the bf16 shadow
+ * weights and the biases named by `mlp` are rewritten from the master.
+ * grad_out (float[SA_MLP_FLAT], nullable) receives the summed gradients and,
+ * at index SA_MLP_PARAMS, the batch loss.  n in [1, 2^20]. */
+size_t sa_surrogate_train_workspace_bytes(int64_t n);
+sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step,
+                                  float lr, const float *feat, const float *target, int64_t n, float *grad_out,
+                                  void *workspace, size_t workspace_bytes, void *stream);
 
 /* Tile size (evaluations per wave) the next sa_score / sa_occupancy /
  * sa_topk calls on this thread use; 0 restores the library's choice.  Must

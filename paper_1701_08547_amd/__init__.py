@@ -7,6 +7,6 @@ package holds its thin ctypes binding (``api``), the seeded input generators
 """
 from . import workloads  # noqa: F401
 from .api import (  # noqa: F401
-    Plan, SAError, Workspace, arch_default, arch_gfx950, arch_validate, autotune, device_batch, occupancy, plan_layout,
-    score, set_tile, topk, workspace_bytes,
+    Plan, SAError, Surrogate, Workspace, arch_default, arch_gfx950, arch_validate, autotune, device_batch, features,
+    occupancy, plan_layout, score, set_tile, topk, workspace_bytes,
 )

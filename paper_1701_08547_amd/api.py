@@ -37,8 +37,12 @@ EXPORTED = (
     "sa_status_string", "sa_last_error", "sa_arch_gfx950", "sa_arch_default_gfx950", "sa_arch_validate",
     "sa_workspace_bytes", "sa_occupancy", "sa_score", "sa_topk", "sa_set_tile",
     "sa_plan_create", "sa_plan_destroy", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
-    "sa_plan_autotune_workspace_bytes", "sa_plan_autotune",
+    "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
+    "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
 )
+MLP_PARAMS = 20865
+MLP_FLAT = 20992
+N_FEAT = 24
 
 
 class SaArch(ctypes.Structure):
@@ -51,6 +55,10 @@ class SaVariants(ctypes.Structure):
 
 class SaConfigs(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in CONFIG_COLUMNS]
+
+
+class SaMlp(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("W1", "W2", "w3", "b1", "b2", "b3", "feat_mean", "feat_inv_std")]
 
 
 class SaPlanShape(ctypes.Structure):
@@ -116,6 +124,15 @@ def lib():
             L.sa_plan_autotune.argtypes = [vp, i64, i64, i32, P(SaArch), P(SaVariants), P(SaConfigs), vp, vp, vp, vp,
                                            vp, sz, vp, i32, PS, P(ctypes.c_float)]
             L.sa_plan_autotune.restype = i32
+            L.sa_features.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp]
+            L.sa_features.restype = i32
+            L.sa_surrogate_fwd.argtypes = [P(SaMlp), vp, i64, vp, vp]
+            L.sa_surrogate_fwd.restype = i32
+            L.sa_surrogate_train_workspace_bytes.argtypes = [i64]
+            L.sa_surrogate_train_workspace_bytes.restype = sz
+            L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64, vp, vp, sz,
+                                                  vp]
+            L.sa_surrogate_train_step.restype = i32
             _lib = L
     return _lib
 
@@ -448,3 +465,130 @@ def autotune(arch: dict, variants: dict, configs: dict, k: int = 8, reps: int = 
                                   _ptr(o["idx"], torch.int32), _ptr(o["val"], torch.float32), ws.ptr, ws.nbytes,
                                   _stream(stream), int(reps), ctypes.byref(best), ctypes.byref(ms)))
     return (best.tile, best.items_per_lane, best.waves_per_block), float(ms.value)
+
+
+# ------------------------------------------------------------------ learned correction
+
+# offsets of the flat fp32 parameter vector
+FLAT_W1, FLAT_B1 = 0, 128 * 32
+FLAT_W2 = FLAT_B1 + 128
+FLAT_B2 = FLAT_W2 + 128 * 128
+FLAT_W3 = FLAT_B2 + 128
+FLAT_B3 = FLAT_W3 + 128
+
+
+def features(arch: dict, variants: dict, configs: dict, out=None, stream=None):
+    """The 24 features of every evaluation (float32 [n_evals, 24])."""
+    torch = _torch()
+    n_var, n_evals = _sizes(variants, configs)
+    if out is None:
+        out = torch.empty((n_evals, N_FEAT), dtype=torch.float32, device=configs["seg"].device)
+    a = _arch_struct(arch)
+    _check(lib().sa_features(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
+                             ctypes.byref(_configs_struct(configs)), n_var, n_evals, _ptr(out, torch.float32, "out"),
+                             _stream(stream)))
+    return out
+
+
+def flat_from_params(p: dict):
+    """Pack a dict of numpy parameters (W1 128x32, b1, W2, b2, w3, b3) into the
+    flat float32 layout."""
+    flat = np.zeros(MLP_FLAT, np.float32)
+    flat[FLAT_W1:FLAT_B1] = np.asarray(p["W1"], np.float32).reshape(-1)
+    flat[FLAT_B1:FLAT_W2] = p["b1"]
+    flat[FLAT_W2:FLAT_B2] = np.asarray(p["W2"], np.float32).reshape(-1)
+    flat[FLAT_B2:FLAT_W3] = p["b2"]
+    flat[FLAT_W3:FLAT_B3] = p["w3"]
+    flat[FLAT_B3] = np.asarray(p["b3"]).reshape(-1)[0]
+    return flat
+
+
+def params_from_flat(flat) -> dict:
+    f = np.asarray(flat, np.float32)
+    return {"W1": f[FLAT_W1:FLAT_B1].reshape(128, 32).copy(), "b1": f[FLAT_B1:FLAT_W2].copy(),
+            "W2": f[FLAT_W2:FLAT_B2].reshape(128, 128).copy(), "b2": f[FLAT_B2:FLAT_W3].copy(),
+            "w3": f[FLAT_W3:FLAT_B3].copy(), "b3": f[FLAT_B3:FLAT_B3 + 1].copy()}
+
+
+class Surrogate:
+    """Device state of the learned correction: fp32 master weights and Adam
+    moments (flat layout), the bf16 shadow the kernels read, and the
+    feature normalisation."""
+
+    def __init__(self, params: dict, mean, inv_std, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        flat = flat_from_params(params)
+        self.master = torch.from_numpy(flat).to(self.device)
+        self.m = torch.zeros(MLP_FLAT, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(MLP_FLAT, dtype=torch.float32, device=self.device)
+        self.grad = torch.zeros(MLP_FLAT, dtype=torch.float32, device=self.device)
+        self.mean = torch.as_tensor(np.asarray(mean, np.float32), device=self.device).contiguous()
+        self.inv_std = torch.as_tensor(np.asarray(inv_std, np.float32), device=self.device).contiguous()
+        self.step_count = 0
+        self.W1 = torch.empty((128, 32), dtype=torch.bfloat16, device=self.device)
+        self.W2 = torch.empty((128, 128), dtype=torch.bfloat16, device=self.device)
+        self.w3 = torch.empty(128, dtype=torch.bfloat16, device=self.device)
+        self.b1 = torch.empty(128, dtype=torch.float32, device=self.device)
+        self.b2 = torch.empty(128, dtype=torch.float32, device=self.device)
+        self.b3 = torch.empty(1, dtype=torch.float32, device=self.device)
+        self.refresh_shadow()
+        self._ws = None
+
+    def refresh_shadow(self):
+        """bf16 shadow and biases from the master weights (round to nearest even)."""
+        mst = self.master
+        self.W1.copy_(mst[FLAT_W1:FLAT_B1].view(128, 32).to(self.W1.dtype))
+        self.W2.copy_(mst[FLAT_W2:FLAT_B2].view(128, 128).to(self.W2.dtype))
+        self.w3.copy_(mst[FLAT_W3:FLAT_B3].to(self.w3.dtype))
+        self.b1.copy_(mst[FLAT_B1:FLAT_W2])
+        self.b2.copy_(mst[FLAT_B2:FLAT_W3])
+        self.b3.copy_(mst[FLAT_B3:FLAT_B3 + 1])
+
+    def struct(self) -> SaMlp:
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        return SaMlp(p(self.W1), p(self.W2), p(self.w3), p(self.b1), p(self.b2), p(self.b3), p(self.mean),
+                     p(self.inv_std))
+
+    def forward(self, feat, out=None, stream=None):
+        torch = _torch()
+        n = int(feat.shape[0])
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=feat.device)
+        m = self.struct()
+        _check(lib().sa_surrogate_fwd(ctypes.byref(m), _ptr(feat, torch.float32, "feat"), n,
+                                      _ptr(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def train_step(self, feat, target, lr: float = 1e-3, stream=None):
+        """One Adam step on the batch; returns the batch loss (0-d device tensor)."""
+        torch = _torch()
+        n = int(feat.shape[0])
+        need = int(lib().sa_surrogate_train_workspace_bytes(n))
+        if self._ws is None or self._ws.nbytes < need:
+            self._ws = Workspace(need, self.device)
+        self.step_count += 1
+        m = self.struct()
+        _check(lib().sa_surrogate_train_step(ctypes.byref(m), _ptr(self.master, torch.float32),
+                                             _ptr(self.m, torch.float32), _ptr(self.v, torch.float32),
+                                             self.step_count, float(lr), _ptr(feat, torch.float32, "feat"),
+                                             _ptr(target, torch.float32, "target"), n,
+                                             _ptr(self.grad, torch.float32), self._ws.ptr, self._ws.nbytes,
+                                             _stream(stream)))
+        return self.grad[MLP_PARAMS]
+
+    def params(self) -> dict:
+        return params_from_flat(self.master.cpu().numpy())
+
+    def state_dict(self) -> dict:
+        return {"master": self.master.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
+                "step": self.step_count, "mean": self.mean.cpu().numpy(), "inv_std": self.inv_std.cpu().numpy()}
+
+    @classmethod
+    def from_state(cls, st: dict, device="cuda"):
+        s = cls(params_from_flat(st["master"]), st["mean"], st["inv_std"], device)
+        torch = _torch()
+        s.m.copy_(torch.from_numpy(np.asarray(st["m"], np.float32)))
+        s.v.copy_(torch.from_numpy(np.asarray(st["v"], np.float32)))
+        s.step_count = int(st["step"])
+        return s

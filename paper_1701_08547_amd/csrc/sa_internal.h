@@ -98,6 +98,50 @@ struct PlanShape {
   int32_t tile, items, wpb;
 };
 
+// ---------------------------------------------------------------- learned correction
+
+struct MlpDev {
+  const uint16_t *W1, *W2, *w3;  // bf16: [128][32], [128][128], [128]
+  const float *b1, *b2, *b3;     // [128], [128], [1]
+  const float *mean, *inv_std;   // [24]
+};
+
+// Flat parameter / gradient layout (fp32 master weights, Adam moments,
+// per-slab gradient partials): W1 | b1 | W2 | b2 | w3 | b3 | loss.
+constexpr int64_t kPartW1 = 0;
+constexpr int64_t kPartB1 = kPartW1 + 128 * 32;
+constexpr int64_t kPartW2 = kPartB1 + 128;
+constexpr int64_t kPartB2 = kPartW2 + 128 * 128;
+constexpr int64_t kPartW3 = kPartB2 + 128;
+constexpr int64_t kPartB3 = kPartW3 + 128;
+constexpr int64_t kPartUsed = kPartB3 + 1;  // parameters
+constexpr int64_t kPartLoss = kPartUsed;    // sum of squared errors
+constexpr int64_t kPartStride = 20992;      // >= kPartLoss + 1, multiple of 256
+
+struct TrainBufs {
+  uint16_t *x;              // [n][32] normalised inputs, bf16
+  float *a1, *a2;           // [n][128] pre-activations
+  uint16_t *h1, *h2;        // [n][128] activations, bf16
+  uint16_t *ga1, *ga2;      // [n][128] dL/da, bf16
+  float *delta, *gdelta, *sq;
+  float *part;              // [slabs][kPartStride]
+};
+
+struct TrainState {
+  float *master, *m, *v;    // [kPartStride]
+};
+
+struct AdamArgs {
+  float lr, beta1, beta2, eps, bc1, bc2;  // bc = 1 - beta^t
+  float inv_n;
+};
+
+hipError_t launch_features(const EvalLaunch &L, float *feat, hipStream_t stream);
+hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream);
+int64_t train_slabs(int64_t n);
+hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,
+                             TrainBufs T, AdamArgs h, float *grad_out, hipStream_t stream);
+
 hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream);
 hipError_t launch_plan(const EvalLaunch &L, const PlanDev &P, const PlanShape &S, Mode mode, bool has_grid, bool topk,
                        int n_cu, hipStream_t stream);
