@@ -91,9 +91,10 @@ def features_from_terms(v: dict, T, U, R, G, n_cu, terms: dict) -> np.ndarray:
     f[:, 18] = terms["W"] / 32.0
     inten = v["n_fp"] / max(1.0, float(v["n_ld"] + v["n_st"]))
     f[:, 19] = math.log1p(inten)
-    f[:, 20] = np.log(terms["Eprime"])
-    f[:, 21] = 1.0 / terms["F"]
-    f[:, 22] = np.log(terms["score"])
+    with np.errstate(divide="ignore", invalid="ignore"):  # illegal rows: F = 0, score = inf
+        f[:, 20] = np.log(terms["Eprime"])
+        f[:, 21] = 1.0 / terms["F"]
+        f[:, 22] = np.log(terms["score"])
     f[:, 23] = 1.0 if inten > 4.0 else 0.0
     return f.astype(np.float32)
 

@@ -565,16 +565,16 @@ class Surrogate:
         torch = _torch()
         n = int(feat.shape[0])
         need = int(lib().sa_surrogate_train_workspace_bytes(n))
-        if self._ws is None or self._ws.nbytes < need:
+        if need and (self._ws is None or self._ws.nbytes < need):
             self._ws = Workspace(need, self.device)
-        self.step_count += 1
+        ws_ptr, ws_bytes = (self._ws.ptr, self._ws.nbytes) if self._ws is not None else (None, 0)
         m = self.struct()
         _check(lib().sa_surrogate_train_step(ctypes.byref(m), _ptr(self.master, torch.float32),
                                              _ptr(self.m, torch.float32), _ptr(self.v, torch.float32),
-                                             self.step_count, float(lr), _ptr(feat, torch.float32, "feat"),
+                                             self.step_count + 1, float(lr), _ptr(feat, torch.float32, "feat"),
                                              _ptr(target, torch.float32, "target"), n,
-                                             _ptr(self.grad, torch.float32), self._ws.ptr, self._ws.nbytes,
-                                             _stream(stream)))
+                                             _ptr(self.grad, torch.float32), ws_ptr, ws_bytes, _stream(stream)))
+        self.step_count += 1
         return self.grad[MLP_PARAMS]
 
     def params(self) -> dict:

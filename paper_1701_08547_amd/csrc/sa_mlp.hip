@@ -198,7 +198,8 @@ __device__ __forceinline__ void make_features(float *f, int32_t nfp, int32_t nin
   f[20] = logf(Ed);
   f[21] = 1.0f / F;
   f[22] = logf(sc);
-  f[23] = inten > 4.0f ? 1.0f : 0.0f;
+  // decided on the integers: n_fp / m > 4 exactly when n_fp > 4 m
+  f[23] = nfp > 4 * (mem > 1 ? mem : 1) ? 1.0f : 0.0f;
 }
 
 // Standalone feature builder over a CSR batch (training data, tests): one

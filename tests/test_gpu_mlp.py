@@ -1,0 +1,215 @@
+"""GPU parity of the learned correction against its binary64 oracle.
+
+Bars (derived from the arithmetic: the GPU rounds h1, h2 and x to bfloat16
+exactly as the oracle does, so the only differences are binary32 rounding of
+the accumulations and of GELU, and bfloat16 ties decided differently):
+  * features: binary32 values within 4e-6 relative of the oracle's rounded
+    binary64 features (ln E', 1/F, ln score within 2e-5: they start from the
+    binary32 score, itself within 1e-5 of binary64), the indicator exact;
+  * forward: |Delta_gpu - Delta_oracle| <= 2^-7 (1 + |Delta|);
+  * one training step: gradients within 2e-2 relative L2 per tensor and
+    cosine >= 0.999; the loss within 2^-6 relative; Adam on the returned
+    gradients within binary32 rounding of the binary64 update.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1701_08547_amd import api, workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+NAMES = ("W1", "b1", "W2", "b2", "w3", "b3")
+
+
+def say(*a):
+    print("[gpu-mlp]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_features(batch, arch):
+    rows = []
+    for v in range(batch.n_var):
+        lo, hi = int(batch.seg[v]), int(batch.seg[v + 1])
+        vv = {k: a[v] for k, a in batch.variants.items()}
+        G = None if batch.grid is None else batch.grid[lo:hi]
+        if hi > lo:
+            rows.append(oracle.features(arch, vv, batch.block[lo:hi], batch.unroll[lo:hi], batch.regs[lo:hi], G))
+    return np.concatenate(rows) if rows else np.zeros((0, 24), np.float32)
+
+
+def legal_mask(batch, arch):
+    return np.isfinite(oracle.run(arch, batch.variants, batch.configs(), k=0)["score64"])
+
+
+def feature_batch(seed, sizes, with_grid=True):
+    return workloads.custom_batch(seed, sizes, with_grid=with_grid, name="feat%d" % seed)
+
+
+def norm_stats(f):
+    mean = f.mean(0).astype(np.float32)
+    sd = f.std(0)
+    inv = np.where(sd > 0, 1.0 / np.maximum(sd, 1e-12), 1.0).astype(np.float32)
+    return mean, inv
+
+
+def surrogate(seed, f):
+    mean, inv = norm_stats(f)
+    p = mlp.init_params(seed=seed)
+    return p, mean, inv, api.Surrogate(p, mean, inv)
+
+
+@pytest.mark.parametrize("with_grid", [True, False])
+def test_features_match_oracle(with_grid):
+    arch = oracle.arch_cdna4()
+    b = feature_batch(1 if with_grid else 2, [1, 63, 64, 65, 1000, 0, 4097], with_grid)
+    say("features", b.n_var, b.n_evals, "grid", with_grid)
+    var, cfg = api.device_batch(b)
+    got = api.features(arch, var, cfg).cpu().numpy()
+    ref = oracle_features(b, arch)
+    ok = legal_mask(b, arch)
+    assert ok.sum() > 100
+    g, r = got[ok].astype(np.float64), ref[ok].astype(np.float64)
+    tol = np.full(24, 4e-6)
+    tol[[20, 21, 22]] = 2e-5
+    err = np.abs(g - r) / np.maximum(1.0, np.abs(r))
+    worst = err.max(0)
+    assert np.all(worst <= tol), dict(zip(mlp.FEATURES, worst))
+    assert np.array_equal(g[:, 23], r[:, 23])
+    # illegal rows are flagged by an infinite ln score
+    assert np.all(np.isinf(got[~ok][:, 22]))
+
+
+def test_features_paper_descriptor():
+    arch = oracle.arch_paper("kepler")
+    b = feature_batch(3, [300, 17])
+    var, cfg = api.device_batch(b)
+    got = api.features(arch, var, cfg).cpu().numpy()
+    ref = oracle_features(b, arch)
+    ok = legal_mask(b, arch)
+    err = np.abs(got[ok].astype(np.float64) - ref[ok]) / np.maximum(1.0, np.abs(ref[ok]))
+    assert err.max() <= 2e-5
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 20001])
+def test_forward_matches_oracle(n):
+    arch = oracle.arch_cdna4()
+    b = feature_batch(10 + n % 7, [3 * n + 64])
+    ok = legal_mask(b, arch)
+    f = oracle_features(b, arch)[ok][:n]
+    assert f.shape[0] == n
+    p, mean, inv, s = surrogate(5, f)
+    say("forward n", n)
+    got = s.forward(torch.from_numpy(f).cuda()).cpu().numpy().astype(np.float64)
+    x = mlp.normalise(f, mean, inv)
+    want = mlp.forward(p, x)["delta"]
+    err = np.abs(got - want) / (1.0 + np.abs(want))
+    assert err.max() <= 2 ** -7, (err.max(), int(err.argmax()))
+    # the inputs are not all alike: the network does discriminate rows
+    assert n < 10 or np.std(want) > 1e-3
+
+
+def test_forward_trained_scale_weights():
+    """Weights several times larger than at initialisation (a trained net)."""
+    arch = oracle.arch_cdna4()
+    b = feature_batch(21, [5000])
+    f = oracle_features(b, arch)[legal_mask(b, arch)]
+    mean, inv = norm_stats(f)
+    p = mlp.init_params(seed=9)
+    for k in ("W1", "W2", "w3"):
+        p[k] = (p[k] * 3.0).astype(np.float32)
+    p["b1"] = np.linspace(-0.5, 0.5, 128).astype(np.float32)
+    p["b2"] = np.linspace(0.3, -0.3, 128).astype(np.float32)
+    p["b3"] = np.array([0.25], np.float32)
+    s = api.Surrogate(p, mean, inv)
+    got = s.forward(torch.from_numpy(f).cuda()).cpu().numpy().astype(np.float64)
+    want = mlp.forward(p, mlp.normalise(f, mean, inv))["delta"]
+    assert (np.abs(got - want) / (1.0 + np.abs(want))).max() <= 2 ** -7
+
+
+def _grads_flat(grad):
+    g = api.params_from_flat(grad)
+    return {k: np.asarray(g[k], np.float64).reshape(-1) for k in NAMES}
+
+
+@pytest.mark.parametrize("n", [1, 100, 256, 1000, 70000])
+def test_train_step_gradients_and_adam(n):
+    arch = oracle.arch_cdna4()
+    b = feature_batch(30 + n % 11, [3 * n + 64])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:n]
+    assert f.shape[0] == n
+    p, mean, inv, s = surrogate(7, f)
+    rng = np.random.default_rng(n)
+    target = (0.3 * np.tanh(f[:, 22] - f[:, 22].mean()) + 0.05 * rng.standard_normal(n)).astype(np.float32)
+    say("train step n", n)
+    lr = 1e-3
+    master0 = s.master.cpu().numpy().copy()
+    loss = float(s.train_step(torch.from_numpy(f).cuda(), torch.from_numpy(target).cuda(), lr=lr).item())
+    torch.cuda.synchronize()
+    grad = s.grad.cpu().numpy()
+    x = mlp.normalise(f, mean, inv)
+    ref_loss, ref_g, _ = mlp.loss_and_grads(p, x, target)
+    assert abs(loss - ref_loss) <= 2 ** -6 * ref_loss, (loss, ref_loss)
+    got = _grads_flat(grad)
+    for k in NAMES:
+        r = np.asarray(ref_g[k], np.float64).reshape(-1)
+        g = got[k]
+        nr = np.linalg.norm(r)
+        if nr == 0:
+            assert np.all(g == 0), k
+            continue
+        rel = np.linalg.norm(g - r) / nr
+        cos = float(g @ r) / (np.linalg.norm(g) * nr)
+        assert rel <= 2e-2 and cos >= 0.999, (k, rel, cos)
+    # padding columns of W1 stay exactly zero
+    W1 = s.master.cpu().numpy()[: 128 * 32].reshape(128, 32)
+    assert np.all(W1[:, 24:] == 0)
+    # Adam applied to the GPU's own gradients, in binary64
+    g_used = api.params_from_flat(grad)
+    new = mlp.adam_step(api.params_from_flat(master0), {k: np.asarray(g_used[k], np.float64) for k in NAMES}, {},
+                        lr=lr)
+    cur = api.params_from_flat(s.master.cpu().numpy())
+    for k in NAMES:
+        d = np.abs(np.asarray(cur[k], np.float64) - np.asarray(new[k], np.float64))
+        tol = 2e-7 + 2 ** -22 * np.abs(np.asarray(new[k], np.float64))
+        assert np.all(d <= tol), (k, d.max())
+    # the bf16 shadow the kernels read is the master rounded to nearest even
+    w2 = s.W2.float().cpu().numpy().astype(np.float64).reshape(-1)
+    assert np.array_equal(w2, mlp.bf16(cur["W2"].reshape(-1)))
+
+
+def test_training_reduces_loss():
+    arch = oracle.arch_cdna4()
+    b = feature_batch(40, [6000])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:4096]
+    p, mean, inv, s = surrogate(11, f)
+    # a smooth function of the static features to be learned
+    target = (0.5 * np.sin(f[:, 9] * 6.0) + 0.3 * f[:, 17] - 0.2 * f[:, 21]).astype(np.float32)
+    target -= target.mean()
+    ft, tt = torch.from_numpy(f).cuda(), torch.from_numpy(target).cuda()
+    losses = [float(s.train_step(ft, tt, lr=3e-3).item()) for _ in range(200)]
+    say("loss", losses[0], losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+    # the trained forward still matches the oracle on the final weights
+    got = s.forward(ft).cpu().numpy().astype(np.float64)
+    want = mlp.forward(s.params(), mlp.normalise(f, mean, inv))["delta"]
+    assert (np.abs(got - want) / (1.0 + np.abs(want))).max() <= 2 ** -7
+
+
+def test_surrogate_errors():
+    f = torch.zeros((4, 24), device="cuda")
+    s = api.Surrogate(mlp.init_params(seed=0), np.zeros(24, np.float32), np.ones(24, np.float32))
+    assert s.forward(f[:0]).shape[0] == 0  # n = 0 is a no-op
+    with pytest.raises(api.SAError):
+        s.train_step(f[:0], torch.zeros(0, device="cuda"))
+    with pytest.raises(api.SAError):
+        s.train_step(f, torch.zeros(4, device="cuda"), lr=0.0)
+    with pytest.raises(api.SAError):
+        s.train_step(f, torch.zeros(4, device="cuda"), lr=float("nan"))
