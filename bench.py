@@ -6,8 +6,8 @@ top-8 selection, with occupancy and score written out) over the batch of
 1,000 kernel variants x 16,384 launch configurations (block x unroll x
 registers x grid, 16,384,000 evaluations), inputs resident in HBM.  The step
 is one persistent-kernel launch over a plan whose launch shape the library's
-autotuner picks at start-up (outside the timed region); the timed steps are
-replays of a HIP graph holding that launch.
+autotuner picks at start-up (outside the timed region); the K timed steps
+are one replay of a HIP graph holding K such launches back to back.
 
 Prints ONE JSON line (rank 0):
   value        configurations scored per second (whole job)
@@ -117,7 +117,14 @@ def main():
         "idx": torch.empty((n_var, K), dtype=torch.int32, device=dev),
         "val": torch.empty((n_var, K), dtype=torch.float32, device=dev),
     }
-    shape, tune_ms = api.autotune(arch, var, cfg, k=K, reps=3, outputs=outs)
+    # bring the clocks up before the autotuner measures anything
+    plan0 = api.Plan(batch.seg, k=K)
+    ws0 = api.Workspace(plan0.workspace_bytes, dev)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.5:
+        plan0.score(arch, var, cfg, outputs=outs, workspace=ws0)
+    torch.cuda.synchronize()
+    shape, tune_ms = api.autotune(arch, var, cfg, k=K, reps=10, outputs=outs)
     plan = api.Plan(batch.seg, k=K, shape=shape)
     ws = api.Workspace(plan.workspace_bytes, dev)
 
@@ -133,21 +140,23 @@ def main():
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        step()
+        for _ in range(args.steps):
+            step()
+    torch.cuda.synchronize()
+    graph.replay()  # first replay uploads the graph
     torch.cuda.synchronize()
 
+    # the graph's kernels run on the stream that replays it: the events go there
     stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
-        graph.replay()
-        b.record(stream)
+    ev0.record(stream)
+    graph.replay()
+    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
-    mean_ms = sum(per_launch_ms) / len(per_launch_ms)
+    mean_ms = ev0.elapsed_time(ev1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
 
     value = n_evals * args.steps / wall
@@ -189,9 +198,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "sa_plan_kernel, one launch per step (HIP events around each graph replay)",
+            "kernel": "sa_plan_kernel, one launch per step (HIP events around the K-launch graph replay)",
             "event_ms_mean": mean_ms,
-            "event_ms_median": per_launch_ms[len(per_launch_ms) // 2],
         },
     }
     if not args.no_cpu_baseline:

@@ -99,8 +99,8 @@ def lib():
             L.sa_workspace_bytes.restype = sz
             L.sa_occupancy.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp]
             L.sa_occupancy.restype = i32
-            L.sa_score.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp, vp, vp,
-                                   sz, vp]
+            L.sa_score.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp,
+                                   P(SaMlp), vp, sz, vp]
             L.sa_score.restype = i32
             L.sa_topk.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp, sz, vp]
             L.sa_topk.restype = i32
@@ -270,12 +270,14 @@ class Workspace:
 
 def score(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: bool = True,
           want_occ: bool = True, want_topk: bool = True, outputs: dict | None = None,
-          workspace: Workspace | None = None, stream=None) -> dict:
+          workspace: Workspace | None = None, stream=None, mlp: "Surrogate | None" = None) -> dict:
     """Occupancy, score and per-variant top-k in one pass (sa_score).
 
     Returns a dict with ``occ`` (int32[n_evals]), ``score`` (float32[n_evals]),
     ``idx`` (int32[n_var, k]) and ``val`` (float32[n_var, k]); entries not
-    requested are None.  `outputs` may supply preallocated tensors.
+    requested are None.  `outputs` may supply preallocated tensors.  With
+    `mlp` (a Surrogate) the pass is the corrected one: ``score`` holds the
+    corrected key z = ln(score) + Delta and the top-k ranks by z.
     """
     torch = _torch()
     n_var, n_evals = _sizes(variants, configs)
@@ -302,8 +304,8 @@ def score(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: 
                           _ptr(o["score"] if want_score else None, torch.float32, "score"),
                           _ptr(o["occ"] if want_occ else None, torch.int32, "occ"), int(k) if want_topk else 0,
                           _ptr(o["idx"] if want_topk else None, torch.int32, "idx"),
-                          _ptr(o["val"] if want_topk else None, torch.float32, "val"), None,
-                          ws_ptr, ws_bytes, _stream(stream)))
+                          _ptr(o["val"] if want_topk else None, torch.float32, "val"),
+                          None if mlp is None else ctypes.byref(mlp.struct()), ws_ptr, ws_bytes, _stream(stream)))
     return o
 
 

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa.so")
-SOURCES = ["sa_api.hip", "sa_eval.hip", "sa_plan.hip", "sa_mlp.hip", "sa_mlp_api.hip"]
+SOURCES = ["sa_api.hip", "sa_eval.hip", "sa_plan.hip", "sa_mlp.hip", "sa_mlp_api.hip", "sa_corrected.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -143,6 +143,9 @@ sa_status bind_workspace(sa::EvalLaunch &L, void *workspace, size_t workspace_by
   return SA_OK;
 }
 
+sa_status check_mlp(const sa_mlp *m);  // sa_mlp_api.hip
+sa::MlpDev mlp_dev(const sa_mlp *m);
+
 sa_status check_variants(const sa_variants *v, int64_t n_var) {
   if (!v) return fail(SA_ERR_ARG, "variants is NULL");
   if (n_var == 0) return SA_OK;
@@ -303,7 +306,7 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   if ((st = check_sizes(n_variants, n_evals)) != SA_OK) return st;
   if ((st = check_variants(variants, n_variants)) != SA_OK) return st;
   if ((st = check_configs(configs, n_evals, true)) != SA_OK) return st;
-  if (mlp) return fail(SA_ERR_UNSUPPORTED, "the corrected mode is not available through sa_score yet");
+  if (mlp && (st = check_mlp(mlp)) != SA_OK) return st;
   const bool topk = topk_idx || topk_val;
   if (topk && (k < 1 || k > SA_K_MAX)) return fail(SA_ERR_ARG, "k = %d outside [1, %d]", k, SA_K_MAX);
   if (!topk && !score && !occ_waves) return fail(SA_ERR_ARG, "no output requested");
@@ -322,7 +325,8 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   L.topk_idx = topk_idx;
   L.topk_val = topk_val;
   L.k = topk ? k : 0;
-  L.tile = pick_tile(n_evals);
+  // the corrected pass does ~100x the work per evaluation: smallest tiles
+  L.tile = mlp ? (g_tile > 0 ? g_tile : sa::kTileMin) : pick_tile(n_evals);
   L.n_tiles = ceil_div(n_evals, L.tile);
   L.need_score = (score || topk) ? 1 : 0;
   L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves, score}) ? 1 : 0;
@@ -332,8 +336,9 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   }
   hipStream_t s = (hipStream_t)stream;
   if (n_evals > 0) {
-    hipError_t e = sa::launch_eval(L, sa::Mode::Model, configs->grid != nullptr, topk, s);
-    if (e != hipSuccess) return hip_fail(e, "sa_eval_kernel launch");
+    hipError_t e = mlp ? sa::launch_corrected(L, mlp_dev(mlp), configs->grid != nullptr, s)
+                       : sa::launch_eval(L, sa::Mode::Model, configs->grid != nullptr, topk, s);
+    if (e != hipSuccess) return hip_fail(e, mlp ? "sa_corrected_kernel launch" : "sa_eval_kernel launch");
   }
   if (topk && n_variants > 0) {
     hipError_t e = sa::launch_merge(L, s);

@@ -137,6 +137,7 @@ struct AdamArgs {
 };
 
 hipError_t launch_features(const EvalLaunch &L, float *feat, hipStream_t stream);
+hipError_t launch_corrected(const EvalLaunch &L, const MlpDev &M, bool has_grid, hipStream_t stream);
 hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream);
 int64_t train_slabs(int64_t n);
 hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,

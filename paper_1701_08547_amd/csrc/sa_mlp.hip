@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include "sa_internal.h"
+#include "sa_mlp_dev.h"
 
 namespace sa {
 namespace {
@@ -37,11 +38,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// GELU(a) = a/2 (1 + erf(a / sqrt 2)) and its derivative.
-__device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float a) {
-  return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * expf(-0.5f * a * a) * 0.39894228040143268f;
-}
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
@@ -173,33 +169,8 @@ __device__ __forceinline__ void make_features(float *f, int32_t nfp, int32_t nin
                                               int32_t U, int32_t R, int32_t G, bool has_grid, int32_t n_cu, int32_t WB,
                                               int32_t gw, int32_t gr, int32_t gs, int32_t B, int32_t W, float Ed,
                                               float F, float sc) {
-  f[0] = log1pf((float)nfp);
-  f[1] = log1pf((float)nint);
-  f[2] = log1pf((float)nld);
-  f[3] = log1pf((float)nst);
-  f[4] = log1pf((float)nbr);
-  f[5] = (float)nbar / 4.0f;
-  f[6] = log1pf((float)nreg);
-  f[7] = (float)S / 65536.0f;
-  f[8] = d;
-  f[9] = log2f((float)T) / 10.0f;
-  f[10] = (float)(U - 1) / 7.0f;
-  f[11] = (float)R / 512.0f;
-  f[12] = has_grid ? log2f((float)G / (float)n_cu) / 3.0f : 0.0f;
-  f[13] = (float)WB / 16.0f;
-  f[14] = (float)(gw < 32 ? gw : 32) / 32.0f;
-  f[15] = (float)(gr < 32 ? gr : 32) / 32.0f;
-  f[16] = (float)(gs < 32 ? gs : 32) / 32.0f;
-  f[17] = (float)B / 32.0f;
-  f[18] = (float)W / 32.0f;
-  const int32_t mem = nld + nst;
-  const float inten = (float)nfp / (float)(mem > 1 ? mem : 1);
-  f[19] = log1pf(inten);
-  f[20] = logf(Ed);
-  f[21] = 1.0f / F;
-  f[22] = logf(sc);
-  // decided on the integers: n_fp / m > 4 exactly when n_fp > 4 m
-  f[23] = nfp > 4 * (mem > 1 ? mem : 1) ? 1.0f : 0.0f;
+  variant_features(f, nfp, nint, nld, nst, nbr, nbar, nreg, S, d);
+  config_features(f, T, U, R, G, has_grid, n_cu, WB, gw, gr, gs, B, W, Ed, F, sc);
 }
 
 // Standalone feature builder over a CSR batch (training data, tests): one
@@ -281,36 +252,33 @@ __global__ void sa_features_kernel(EvalLaunch L, float *feat) {
 
 // ---------------------------------------------------------------- inference
 
-// Delta for n rows of raw features (n x 24 fp32).
-__global__ __launch_bounds__(kMlpThreads) void sa_mlp_fwd_kernel(MlpDev M, const float *feat, int64_t n,
-                                                                  float *delta) {
-  __shared__ MlpLds s;
-  __shared__ WaveBufs wbuf[kMlpWaves];
+// Delta for n rows of raw features (n x 24 fp32): each wave takes blocks of
+// 64 rows, one row per lane.
+constexpr int kFwdWaves = 8;
+
+__global__ __launch_bounds__(64 * kFwdWaves) void sa_mlp_fwd_kernel(MlpDev M, const float *feat, int64_t n,
+                                                                    float *delta) {
+  __shared__ MlpLdsT s;
+  __shared__ __align__(16) uint16_t X[kFwdWaves][64 * kLdXT];
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-  load_weights(M, s, tid, kMlpThreads);
+  load_weights_t(M, s, tid, 64 * kFwdWaves);
   __syncthreads();
-  WaveBufs &wb = wbuf[w];
-  const int64_t n_blocks = (n + kRows - 1) / kRows;
-  for (int64_t blk = (int64_t)blockIdx.x * kMlpWaves + w; blk < n_blocks; blk += (int64_t)gridDim.x * kMlpWaves) {
-    const int64_t row = blk * kRows + lane;
+  const int64_t n_blocks = (n + 63) / 64;
+  for (int64_t blk = (int64_t)blockIdx.x * kFwdWaves + w; blk < n_blocks; blk += (int64_t)gridDim.x * kFwdWaves) {
+    const int64_t row = blk * 64 + lane;
+    const bool in = row < n;
     float f[kF];
 #pragma unroll
-    for (int i = 0; i < kF; ++i) f[i] = row < n ? feat[row * kF + i] : 0.0f;
-    put_row(s, wb, lane, f);
-    float d[4][4];
-    forward_block<false>(s, wb, lane, d, FwdStash{});
-    const int r = lane & 15, q = lane >> 4;
-    if (r == 0) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int64_t rr = blk * kRows + 16 * m + 4 * q + j;
-          if (rr < n) delta[rr] = d[m][j];
-        }
-    }
+    for (int i = 0; i < kF; ++i) f[i] = in ? feat[row * kF + i] : 0.0f;
+    put_x(s, X[w], lane, f, !in);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const float d = mlp_rows(s, X[w], lane);
+    if (in) delta[row] = d;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
 }
 
@@ -537,10 +505,10 @@ hipError_t launch_features(const EvalLaunch &L, float *feat, hipStream_t stream)
 
 hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  const int64_t n_blocks = (n + kRows - 1) / kRows;
-  int64_t grid = (n_blocks + kMlpWaves - 1) / kMlpWaves;
+  const int64_t n_blocks = (n + 63) / 64;
+  int64_t grid = (n_blocks + kFwdWaves - 1) / kFwdWaves;
   if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(sa_mlp_fwd_kernel, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, feat, n, delta);
+  hipLaunchKernelGGL(sa_mlp_fwd_kernel, dim3((uint32_t)grid), dim3(64 * kFwdWaves), 0, stream, M, feat, n, delta);
   return hipGetLastError();
 }
 

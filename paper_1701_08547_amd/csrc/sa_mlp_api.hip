@@ -12,15 +12,6 @@ sa_status fail(sa_status st, const char *fmt, ...);
 sa_status check_arch(const sa_arch *a);
 sa::KArch to_karch(const sa_arch *a);
 sa_status hip_fail(hipError_t e, const char *what);
-}  // namespace sa_detail
-
-using sa_detail::fail;
-using sa_detail::hip_fail;
-
-static_assert(sa::kPartUsed == SA_MLP_PARAMS, "parameter layout");
-static_assert(sa::kPartStride == SA_MLP_FLAT, "flat layout");
-
-namespace {
 
 bool a4(const void *p) { return ((uintptr_t)p % 4) == 0; }
 
@@ -34,9 +25,22 @@ sa_status check_mlp(const sa_mlp *m) {
   return SA_OK;
 }
 
-sa::MlpDev to_dev(const sa_mlp *m) {
+sa::MlpDev mlp_dev(const sa_mlp *m) {
   return sa::MlpDev{m->W1, m->W2, m->w3, m->b1, m->b2, m->b3, m->feat_mean, m->feat_inv_std};
 }
+
+}  // namespace sa_detail
+
+using sa_detail::a4;
+using sa_detail::check_mlp;
+using sa_detail::fail;
+using sa_detail::hip_fail;
+using sa_detail::mlp_dev;
+
+static_assert(sa::kPartUsed == SA_MLP_PARAMS, "parameter layout");
+static_assert(sa::kPartStride == SA_MLP_FLAT, "flat layout");
+
+namespace {
 
 // Workspace carve-up of one training step of n rows.
 struct TrainLayout {
@@ -94,7 +98,7 @@ sa_status sa_surrogate_fwd(const sa_mlp *mlp, const float *feat, int64_t n, floa
   if (n == 0) return SA_OK;
   if (!feat || !delta) return fail(SA_ERR_ARG, "NULL argument");
   if (!a4(feat) || !a4(delta)) return fail(SA_ERR_ALIGN, "feat / delta not 4-byte aligned");
-  hipError_t e = sa::launch_mlp_fwd(to_dev(mlp), feat, n, delta, (hipStream_t)stream);
+  hipError_t e = sa::launch_mlp_fwd(mlp_dev(mlp), feat, n, delta, (hipStream_t)stream);
   return e == hipSuccess ? SA_OK : hip_fail(e, "sa_mlp_fwd_kernel launch");
 }
 
@@ -137,7 +141,7 @@ sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_
   h.bc1 = (float)(1.0 - pow(0.9, (double)step));
   h.bc2 = (float)(1.0 - pow(0.999, (double)step));
   h.inv_n = 1.0f / (float)n;
-  hipError_t e = sa::launch_train_step(to_dev(mlp), sa::TrainState{master, adam_m, adam_v}, feat, target, n, T, h,
+  hipError_t e = sa::launch_train_step(mlp_dev(mlp), sa::TrainState{master, adam_m, adam_v}, feat, target, n, T, h,
                                        grad_out, (hipStream_t)stream);
   return e == hipSuccess ? SA_OK : hip_fail(e, "training kernels launch");
 }

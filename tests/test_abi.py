@@ -120,11 +120,16 @@ def test_argument_errors_before_any_launch(L):
                      ctypes.c_void_p(256), 8, None) == -4
     assert L.sa_topk(ctypes.c_void_p(256), ctypes.c_void_p(8), 1, 100, 8, ctypes.c_void_p(16), None,
                      ctypes.c_void_p(128), 1 << 20, None) == -2
-    # the corrected mode is not reachable through sa_score in this build
+    # corrected mode: the network's pointers are checked before any launch
     v2 = api.SaVariants(*([8] * 9))
     c2 = api.SaConfigs(8, 8, 8, 8, None)
-    assert L.sa_score(by(a), by(v2), by(c2), 1, 1, ctypes.c_void_p(8), None, 0, None, None, ctypes.c_void_p(8),
-                      None, 0, None) == -6
+    m_null = api.SaMlp(*([256] * 7 + [None]))
+    assert L.sa_score(by(a), by(v2), by(c2), 1, 1, ctypes.c_void_p(8), None, 0, None, None, by(m_null),
+                      None, 0, None) == -1
+    assert "mlp" in L.sa_last_error().decode()
+    m_odd = api.SaMlp(*([260] + [256] * 7))
+    assert L.sa_score(by(a), by(v2), by(c2), 1, 1, ctypes.c_void_p(8), None, 0, None, None, by(m_odd),
+                      None, 0, None) == -2
 
 
 def test_tile_setter(L):

@@ -1,0 +1,178 @@
+"""GPU tests of the fused corrected scoring pass (sa_score with a network).
+
+Bars:
+  * occupancy bit-exact against the oracle;
+  * the corrected key z of every evaluation bit-identical to the unfused
+    composition of the same library's pieces (sa_features, then
+    sa_surrogate_fwd, then ln score + Delta), +inf exactly on illegal rows;
+  * the top-k (indices and values) bit-identical to sa_topk over that z;
+  * z within the learned correction's band of the oracle's
+    ln(score) + Delta: 2^-7 (1 + |Delta|) + 2e-5 (1 + |ln score|), the
+    second term for the binary32 score and logarithm;
+  * against the oracle's own ranking by z (several answers are correct
+    within the band): every selected index is legal, and its oracle key is
+    no worse than the oracle's k-th key plus twice the band.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1701_08547_amd import api, workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def say(*a):
+    print("[gpu-corrected]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_features(batch, arch):
+    out = np.zeros((batch.n_evals, 24), np.float32)
+    for v in range(batch.n_var):
+        lo, hi = int(batch.seg[v]), int(batch.seg[v + 1])
+        if hi > lo:
+            vv = {k: a[v] for k, a in batch.variants.items()}
+            G = None if batch.grid is None else batch.grid[lo:hi]
+            out[lo:hi] = oracle.features(arch, vv, batch.block[lo:hi], batch.unroll[lo:hi], batch.regs[lo:hi], G)
+    return out
+
+
+def make_surrogate(batch, arch, seed=3, scale=1.0):
+    ref = oracle.run(arch, batch.variants, batch.configs(), k=0)
+    legal = np.isfinite(ref["score64"])
+    f = oracle_features(batch, arch)
+    fl = f[legal]
+    mean = fl.mean(0).astype(np.float32)
+    sd = fl.std(0)
+    inv = np.where(sd > 0, 1.0 / np.maximum(sd, 1e-12), 1.0).astype(np.float32)
+    p = mlp.init_params(seed=seed)
+    for key in ("W1", "W2", "w3"):
+        p[key] = (p[key] * scale).astype(np.float32)
+    p["b3"] = np.array([0.1], np.float32)
+    return p, mean, inv, api.Surrogate(p, mean, inv), ref, f, legal
+
+
+def unfused(arch, var, cfg, sur, n_evals):
+    """z from the unfused pieces: features, forward pass, one binary32 add."""
+    feat = api.features(arch, var, cfg)
+    delta = sur.forward(feat)
+    z = feat[:, 22] + delta
+    return feat, delta, z
+
+
+def check_case(batch, k, arch=None, seed=3, scale=1.0, tile=None):
+    arch = arch or oracle.arch_cdna4()
+    say("case", batch.name, "n_var", batch.n_var, "n_evals", batch.n_evals, "k", k, "tile", tile)
+    p, mean, inv, sur, ref, f_or, legal = make_surrogate(batch, arch, seed, scale)
+    var, cfg = api.device_batch(batch)
+    if tile:
+        api.set_tile(tile)
+    try:
+        got = api.score(arch, var, cfg, k=k, mlp=sur)
+    finally:
+        api.set_tile(0)
+    feat, delta, z_ref = unfused(arch, var, cfg, sur, batch.n_evals)
+    torch.cuda.synchronize()
+    occ = got["occ"].cpu().numpy()
+    z = got["score"].cpu().numpy()
+    assert np.array_equal(occ, ref["occ"])
+    # composition: bit-identical z, +inf exactly where illegal
+    zr = z_ref.cpu().numpy()
+    zr = np.where(legal, zr, np.float32(np.inf))
+    assert np.array_equal(np.isinf(z) & (z > 0), ~legal)
+    bad = np.flatnonzero(z.view(np.uint32) != zr.view(np.uint32))
+    assert bad.size == 0, (bad[:5], z[bad[:5]], zr[bad[:5]])
+    # top-k equals sa_topk over the same keys
+    seg_t = cfg["seg"]
+    idx_t, val_t = api.topk(got["score"], seg_t, k)
+    assert np.array_equal(got["idx"].cpu().numpy(), idx_t.cpu().numpy())
+    assert np.array_equal(got["val"].cpu().numpy().view(np.uint32), val_t.cpu().numpy().view(np.uint32))
+    # oracle band on z
+    x = mlp.normalise(f_or[legal], mean, inv)
+    d_or = mlp.forward(p, x)["delta"]
+    ln_s = np.log(ref["score64"][legal])
+    z_or = np.full(batch.n_evals, np.inf)
+    z_or[legal] = ln_s + d_or
+    band = 2.0 ** -7 * (1.0 + np.abs(d_or)) + 2e-5 * (1.0 + np.abs(ln_s))
+    err = np.abs(z[legal].astype(np.float64) - z_or[legal])
+    assert np.all(err <= band), (err.max(), int(np.argmax(err - band)))
+    # selection validity against the oracle's ranking
+    idx = got["idx"].cpu().numpy()
+    band_full = np.zeros(batch.n_evals)
+    band_full[legal] = band
+    for v in range(batch.n_var):
+        lo, hi = int(batch.seg[v]), int(batch.seg[v + 1])
+        zo = z_or[lo:hi]
+        n_legal = int(np.isfinite(zo).sum())
+        row = idx[v]
+        assert np.all(row[: min(k, n_legal)] >= 0) and np.all(row[min(k, n_legal):] == -1)
+        if n_legal == 0:
+            continue
+        kth = np.sort(zo)[min(k, n_legal) - 1]
+        sel = row[row >= 0]
+        assert len(set(sel.tolist())) == sel.size
+        # z_gpu(j) <= z_gpu(k-th) <= kth + band, and zo(j) <= z_gpu(j) + band
+        assert np.all(zo[sel] <= kth + 2 * band_full[lo:hi].max())
+    return got
+
+
+def test_corrected_ragged_with_grid():
+    b = workloads.custom_batch(61, [1, 63, 64, 65, 1000, 0, 4097, 2500], name="corr-ragged")
+    check_case(b, 8)
+
+
+def test_corrected_no_grid_k1_k16():
+    b = workloads.custom_batch(62, [500, 3000, 17, 0, 1025], with_grid=False, name="corr-nogrid")
+    check_case(b, 1)
+    check_case(b, 16)
+
+
+def test_corrected_segments_span_tiles():
+    b = workloads.custom_batch(63, [3000, 5000, 1, 2047, 9000], name="corr-span")
+    check_case(b, 8)
+    check_case(b, 8, tile=2048)
+
+
+def test_corrected_trained_scale():
+    b = workloads.custom_batch(64, [4000, 700], name="corr-scale")
+    check_case(b, 8, seed=5, scale=3.0)
+
+
+def test_corrected_paper_descriptor():
+    b = workloads.custom_batch(65, [800, 300], name="corr-kepler")
+    check_case(b, 4, arch=oracle.arch_paper("kepler"))
+
+
+def test_corrected_optional_outputs_and_determinism():
+    arch = oracle.arch_cdna4()
+    b = workloads.custom_batch(66, [2000, 70, 3000], name="corr-opt")
+    _, _, _, sur, _, _, _ = make_surrogate(b, arch)
+    var, cfg = api.device_batch(b)
+    full = api.score(arch, var, cfg, k=8, mlp=sur)
+    only_k = api.score(arch, var, cfg, k=8, mlp=sur, want_score=False, want_occ=False)
+    only_z = api.score(arch, var, cfg, k=8, mlp=sur, want_topk=False, want_occ=False)
+    again = api.score(arch, var, cfg, k=8, mlp=sur)
+    torch.cuda.synchronize()
+    assert torch.equal(full["idx"], only_k["idx"]) and torch.equal(full["val"], only_k["val"])
+    assert torch.equal(full["score"].view(torch.int32), only_z["score"].view(torch.int32))
+    for key in ("occ", "score", "idx", "val"):
+        assert torch.equal(full[key].view(torch.int32), again[key].view(torch.int32)), key
+
+
+def test_corrected_plain_outputs_unchanged_without_network():
+    """The plain pass on the same batch still gives the oracle's scores."""
+    arch = oracle.arch_cdna4()
+    b = workloads.custom_batch(67, [1000, 300])
+    var, cfg = api.device_batch(b)
+    got = api.score(arch, var, cfg, k=8)
+    ref = oracle.run(arch, b.variants, b.configs(), k=8)
+    assert np.array_equal(got["score"].cpu().numpy().view(np.uint32), ref["score32"].view(np.uint32))
+    assert np.array_equal(got["idx"].cpu().numpy(), ref["idx"])
