@@ -1,0 +1,74 @@
+/*
+ * Measured-runtime dataset for the learned correction of the static model:
+ * three parametric kernel families compiled for gfx950, and a native timing
+ * harness.
+ *
+ * The paper tunes kernels by running every candidate configuration and
+ * timing it (Sec. VI: one warm-up, ten timed runs, a fixed order statistic
+ * kept); its static model exists to avoid that cost.  This library produces
+ * such measurements for its own kernels so that a model correction can be
+ * trained and judged on real runtimes: configurations are the paper's
+ * tuning parameters block size T (threads per block) and unroll factor U
+ * (Sec. V, Table IV), with the grid following from the problem size.
+ *
+ * Families (float32 data, problem size n):
+ *   SA_RT_MATVEC   y += A x, A column-major n x n, n a multiple of 840, at
+ *                  most 65,520; block (bx, by) covers T rows and the 840
+ *                  columns of chunk by, one thread per row, one atomic add
+ *                  per thread; main loop of 840 / U steps, U multiply-adds
+ *                  each; G = ceil(n / T) * (n / 840).
+ *   SA_RT_STENCIL  one out-of-place 5-point sweep over the interior of an
+ *                  n x n grid, 3 <= n <= 32,768; a work unit is U consecutive points
+ *                  of a row; grid-stride main loop.
+ *   SA_RT_REDUCE   sum of n < 2^30 values; grid-stride main loop adding U values
+ *                  per step, then a tree reduction in LDS (second loop) and
+ *                  one atomic add per block.
+ * Grid-stride families launch G = min(ceil(units / T), n_cu * max(1, 2048 / T))
+ * blocks, units = the family's work units.
+ *
+ * Every function is synchronous on the host unless it takes a stream;
+ * errors: -1 argument, -5 HIP runtime (message: sa_rt_last_error).
+ */
+#ifndef SA_RUNTIME_H
+#define SA_RUNTIME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SA_RT_MATVEC = 0, SA_RT_STENCIL = 1, SA_RT_REDUCE = 2 };
+
+/* Message of the last failing call on this thread. */
+const char *sa_rt_last_error(void);
+
+/* Blocks launched for (family, n, T, U) on a device of n_cu compute units;
+ * -1 outside the family's domain (T in [1, 1024], U in [1, 8]). */
+int64_t sa_rt_grid(int32_t family, int64_t n, int32_t T, int32_t U, int32_t n_cu);
+
+/* Iterations each thread makes of loop `loop` (0 = main loop, 1 = the
+ * reduction's tree loop) at grid G; an upper bound for threads at the
+ * edges.  -1 for a loop the family does not have. */
+int64_t sa_rt_trips(int32_t family, int64_t n, int32_t T, int32_t U, int64_t G, int32_t loop);
+
+/* Floats of device buffer `which` (0 = a, 1 = b, 2 = c) the family needs at
+ * size n: matvec A / x / y, stencil in / - / out, reduce in / - / out. */
+size_t sa_rt_buffer_floats(int32_t family, int64_t n, int32_t which);
+
+/* Time n_cfg configurations (T[i], U[i]) of one instance on `stream`:
+ * per configuration `warmup` untimed launches, then `reps` (<= 64) launches
+ * each bracketed by HIP events; ms_out[i] = the keep-th smallest duration
+ * (milliseconds).  a, b, c: device buffers of sa_rt_buffer_floats floats,
+ * caller-owned (inputs are read, outputs overwritten).  Blocks until the
+ * timings are read. */
+int32_t sa_rt_measure(int32_t family, int64_t n, const float *a, const float *b, float *c, const int32_t *T,
+                      const int32_t *U, int32_t n_cfg, int32_t n_cu, int32_t warmup, int32_t reps, int32_t keep,
+                      float *ms_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SA_RUNTIME_H */

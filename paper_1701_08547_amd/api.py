@@ -39,6 +39,7 @@ EXPORTED = (
     "sa_plan_create", "sa_plan_destroy", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
+    "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure",
 )
 MLP_PARAMS = 20865
 MLP_FLAT = 20992
@@ -133,6 +134,15 @@ def lib():
             L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64, vp, vp, sz,
                                                   vp]
             L.sa_surrogate_train_step.restype = i32
+            L.sa_rt_last_error.restype = ctypes.c_char_p
+            L.sa_rt_grid.argtypes = [i32, i64, i32, i32, i32]
+            L.sa_rt_grid.restype = i64
+            L.sa_rt_trips.argtypes = [i32, i64, i32, i32, i64, i32]
+            L.sa_rt_trips.restype = i64
+            L.sa_rt_buffer_floats.argtypes = [i32, i64, i32]
+            L.sa_rt_buffer_floats.restype = sz
+            L.sa_rt_measure.argtypes = [i32, i64, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]
+            L.sa_rt_measure.restype = i32
             _lib = L
     return _lib
 

@@ -10,7 +10,11 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa.so")
-SOURCES = ["sa_api.hip", "sa_eval.hip", "sa_plan.hip", "sa_mlp.hip", "sa_mlp_api.hip", "sa_corrected.hip"]
+SOURCES = ["sa_api.hip", "sa_eval.hip", "sa_plan.hip", "sa_mlp.hip", "sa_mlp_api.hip", "sa_corrected.hip",
+           "sa_runtime.hip"]
+# gfx950 assembly of the measured kernel families, read by the static
+# feature extractor (same device flags as the library)
+RUNTIME_ASM = os.path.join(PKG, "sa_runtime_gfx950.s")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -36,7 +40,20 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_runtime_asm(verbose)
     return LIB
+
+
+def build_runtime_asm(verbose: bool = False) -> str:
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    tmp = RUNTIME_ASM + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), *flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "--cuda-device-only", "-S",
+           os.path.join(CSRC, "sa_runtime.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, RUNTIME_ASM)
+    return RUNTIME_ASM
 
 
 if __name__ == "__main__":

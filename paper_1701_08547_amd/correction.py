@@ -1,0 +1,229 @@
+"""Training and evaluation of the learned correction on measured runtimes.
+
+The static model ranks an instance's configurations by ln(score); the
+correction adds Delta(features) so that the corrected key
+z = ln(score) + Delta tracks the measured log-runtime.  Per instance the
+target of a row is its log-runtime residual after removing the per-instance
+medians: r = (ln t - median ln t) - (ln s - median ln s), so that the
+network learns only what the static model gets wrong in the ranking.
+
+Everything numeric runs through the library: features (sa_features),
+training steps (sa_surrogate_train_step) and the corrected keys of the
+evaluation (sa_surrogate_fwd).
+
+Evaluation per held-out instance (10 % of the instances of each family):
+top-1 regret t(argmin key) / min t - 1 (ties to the lower index) and the
+Spearman rank correlation of key and runtime, for the plain and the
+corrected key; means with bootstrap confidence intervals.
+
+CLI (GPU): python -m paper_1701_08547_amd.correction --data runtime.npz \\
+              --epochs 40 --out correction.npz --report correction.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import api
+from .runtime_dataset import COUNT_FIELDS, FAMILIES, N_CFG, load
+
+
+def device_rows(rows: dict, device="cuda"):
+    """The dataset's rows as a device batch with one segment per row."""
+    import torch
+
+    n = rows["ms"].size
+    var = {}
+    for f in COUNT_FIELDS:
+        var[f] = torch.from_numpy(np.ascontiguousarray(rows[f], dtype=np.int32)).to(device)
+    var["lds_bytes"] = torch.from_numpy(np.ascontiguousarray(rows["lds"], dtype=np.int32)).to(device)
+    var["div"] = torch.from_numpy(np.ascontiguousarray(rows["div"], dtype=np.float32)).to(device)
+    cfg = {"seg": torch.arange(n + 1, dtype=torch.int64, device=device)}
+    for f in ("block", "unroll", "regs", "grid"):
+        cfg[f] = torch.from_numpy(np.ascontiguousarray(rows[f], dtype=np.int32)).to(device)
+    return var, cfg
+
+
+def residual_targets(ln_t: np.ndarray, ln_s: np.ndarray) -> np.ndarray:
+    """[n_inst, 128] -> per-row residual of ln t after the plain model."""
+    return ((ln_t - np.median(ln_t, axis=1, keepdims=True)) - (ln_s - np.median(ln_s, axis=1, keepdims=True)))
+
+
+def holdout_split(families: np.ndarray, frac: float = 0.1, seed: int = 0):
+    """Instance indices (train, held_out), `frac` of each family held out."""
+    g = np.random.default_rng(np.random.SeedSequence([170108547, 3, 200 + seed]))
+    train, held = [], []
+    for f in np.unique(families):
+        idx = np.flatnonzero(families == f)
+        g.shuffle(idx)
+        k = max(1, int(round(frac * idx.size)))
+        held += idx[:k].tolist()
+        train += idx[k:].tolist()
+    return np.sort(np.array(train, np.int64)), np.sort(np.array(held, np.int64))
+
+
+def ranks(x: np.ndarray) -> np.ndarray:
+    """Average ranks (ties share the mean of their positions)."""
+    order = np.argsort(x, kind="mergesort")
+    xs = x[order]
+    r = np.empty(x.size, np.float64)
+    i = 0
+    while i < x.size:
+        j = i
+        while j + 1 < x.size and xs[j + 1] == xs[i]:
+            j += 1
+        r[order[i:j + 1]] = 0.5 * (i + j)
+        i = j + 1
+    return r
+
+
+def spearman(a: np.ndarray, b: np.ndarray) -> float:
+    ra, rb = ranks(np.asarray(a, np.float64)), ranks(np.asarray(b, np.float64))
+    ra -= ra.mean()
+    rb -= rb.mean()
+    den = np.sqrt((ra * ra).sum() * (rb * rb).sum())
+    return float((ra * rb).sum() / den) if den > 0 else 0.0
+
+
+def regret(key: np.ndarray, t: np.ndarray) -> float:
+    return float(t[int(np.argmin(key))] / t.min() - 1.0)
+
+
+def bootstrap_ci(x: np.ndarray, reps: int = 2000, seed: int = 0):
+    g = np.random.default_rng(seed)
+    m = np.array([g.choice(x, x.size).mean() for _ in range(reps)])
+    return float(np.quantile(m, 0.025)), float(np.quantile(m, 0.975))
+
+
+def init_params(seed: int) -> dict:
+    """U(+-1/sqrt(fan_in)) weights (padding columns of W1 zero), zero biases."""
+    g = np.random.default_rng(np.random.SeedSequence([170108547, 3, 300 + seed]))
+    W1 = (g.uniform(-1, 1, (128, 32)) / np.sqrt(24)).astype(np.float32)
+    W1[:, 24:] = 0
+    W2 = (g.uniform(-1, 1, (128, 128)) / np.sqrt(128)).astype(np.float32)
+    w3 = (g.uniform(-1, 1, 128) / np.sqrt(128)).astype(np.float32)
+    z = np.zeros(128, np.float32)
+    return {"W1": W1, "b1": z.copy(), "W2": W2, "b2": z.copy(), "w3": w3, "b3": np.zeros(1, np.float32)}
+
+
+def train(feat, target, mean, inv_std, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
+          device="cuda", log=None):
+    """Adam on MSE(Delta, r) over shuffled mini-batches (device tensors feat
+    [n, 24] and target [n]); returns the Surrogate and the per-epoch mean
+    loss."""
+    import torch
+
+    sur = api.Surrogate(init_params(seed), mean, inv_std, device)
+    n = int(feat.shape[0])
+    gen = torch.Generator(device=device)
+    gen.manual_seed(170108547 + seed)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen, device=device)
+        tot = torch.zeros((), dtype=torch.float32, device=device)
+        nb = 0
+        for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
+            idx = perm[b0:b0 + batch]
+            fb = feat.index_select(0, idx).contiguous()
+            tb = target.index_select(0, idx).contiguous()
+            tot += sur.train_step(fb, tb, lr=lr)
+            nb += 1
+        losses.append(float(tot.item()) / max(1, nb))
+        if log:
+            log("epoch %d loss %.5f" % (ep + 1, losses[-1]))
+    return sur, losses
+
+
+def corrected_keys(feat, sur):
+    """z = ln score + Delta of every row: the unfused composition of the
+    features and the forward pass (bit-identical to the fused corrected
+    pass, which pays one workgroup pass per segment on one-row segments)."""
+    return feat[:, 22] + sur.forward(feat)
+
+
+def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, families: np.ndarray) -> dict:
+    """Regret and Spearman of the plain and corrected keys per held-out
+    instance ([n_inst, 128] arrays), overall and per family."""
+    rep = {}
+
+    def block(ids):
+        rp = np.array([regret(ln_s[i], ms[i]) for i in ids])
+        rc = np.array([regret(z[i], ms[i]) for i in ids])
+        sp = np.array([spearman(ln_s[i], ms[i]) for i in ids])
+        sc = np.array([spearman(z[i], ms[i]) for i in ids])
+        return {"instances": int(len(ids)),
+                "regret_plain": float(rp.mean()), "regret_plain_ci": bootstrap_ci(rp),
+                "regret_corrected": float(rc.mean()), "regret_corrected_ci": bootstrap_ci(rc),
+                "regret_diff_ci": bootstrap_ci(rp - rc),
+                "spearman_plain": float(sp.mean()), "spearman_corrected": float(sc.mean())}
+
+    rep["all"] = block(held)
+    for f, name in enumerate(FAMILIES):
+        ids = held[families[held] == f]
+        if ids.size:
+            rep[name] = block(ids)
+    return rep
+
+
+def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0, device="cuda", log=None):
+    import torch
+
+    n_inst = int(data["instance"].max()) + 1
+    arch = api.arch_default(torch.device(device).index or 0)
+    var, cfg = device_rows(data, device)
+    feat = api.features(arch, var, cfg)
+    ln_s = feat[:, 22].cpu().numpy().astype(np.float64).reshape(n_inst, N_CFG)
+    ms = data["ms"].astype(np.float64).reshape(n_inst, N_CFG)
+    legal = np.isfinite(ln_s)
+    if not legal.all():
+        raise ValueError("%d configurations are illegal under the model" % int((~legal).sum()))
+    r = residual_targets(np.log(ms), ln_s)
+    families = data["family"].reshape(n_inst, N_CFG)[:, 0]
+    tr, held = holdout_split(families, 0.1, seed)
+    rows_tr = (tr[:, None] * N_CFG + np.arange(N_CFG)[None, :]).reshape(-1)
+    f_np = feat.cpu().numpy()
+    mean = f_np[rows_tr].mean(0).astype(np.float32)
+    sd = f_np[rows_tr].std(0)
+    inv = np.where(sd > 1e-12, 1.0 / np.maximum(sd, 1e-12), 1.0).astype(np.float32)
+    idx = torch.from_numpy(rows_tr).to(device)
+    f_tr = feat.index_select(0, idx).contiguous()
+    r_tr = torch.from_numpy(r.reshape(-1)[rows_tr].astype(np.float32)).to(device)
+    t0 = time.time()
+    sur, losses = train(f_tr, r_tr, mean, inv, epochs, batch, lr, seed, device, log)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    z = corrected_keys(feat, sur).cpu().numpy().astype(np.float64).reshape(n_inst, N_CFG)
+    rep = evaluate(ms, ln_s, z, held, families)
+    rep["train"] = {"rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
+                    "loss_first": losses[0], "loss_last": losses[-1],
+                    "target_var": float(np.var(r.reshape(-1)[rows_tr]))}
+    return sur, rep
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--data", required=True)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None, help="npz of the trained network state")
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)
+    sur, rep = run(load(a.data), a.epochs, a.batch, a.lr, a.seed, log=log)
+    if a.out:
+        np.savez(a.out, **{k: np.asarray(v) for k, v in sur.state_dict().items()})
+    txt = json.dumps(rep, indent=1)
+    if a.report:
+        with open(a.report, "w") as f:
+            f.write(txt + "\n")
+    print(txt, flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

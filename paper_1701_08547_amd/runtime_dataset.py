@@ -1,0 +1,192 @@
+"""Measured-runtime dataset for the learned correction.
+
+Instances are (family, problem size) pairs of the three parametric kernel
+families built into the library (matvec, 5-point stencil, reduction; see
+``include/sa_runtime.h``).  Each instance is timed at the 128 configurations
+T in {64, 128, ..., 1024} x U in {1, ..., 8} by the native harness with the
+paper's protocol (one warm-up launch, ten timed launches, the fifth smallest
+kept; Sec. VI).  Each (instance, configuration) row also gets the static
+model's inputs, read from the family's own gfx950 code (asm_features):
+per-thread instruction counts (loop bodies times trip counts), registers,
+LDS bytes, a divergence share, block size, unroll factor and grid.
+
+Sizes are log-uniform per family: matvec n in [1024, 32768] (rounded to a
+multiple of 840 in [1680, 32760]), stencil n in [512, 8192], reduction n in [2^20, 2^28];
+inputs N(0, 1).
+
+CLI (GPU): python -m paper_1701_08547_amd.runtime_dataset --per-family 500 \\
+              --out runtime.npz
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import api, asm_features, workloads
+
+FAMILIES = ("matvec", "stencil", "reduce")
+FAMILY_ID = {f: i for i, f in enumerate(FAMILIES)}
+SIZE_RANGE = {"matvec": (1024, 32768), "stencil": (512, 8192), "reduce": (1 << 20, 1 << 28)}
+T_VALUES = np.arange(64, 1025, 64, dtype=np.int32)
+U_VALUES = np.arange(1, 9, dtype=np.int32)
+N_CFG = T_VALUES.size * U_VALUES.size
+DATASET_ID = 3  # seed stream of the measured-runtime workload
+COUNT_FIELDS = ("n_fp", "n_int", "n_ld", "n_st", "n_br", "n_bar", "n_reg")
+
+
+def config_grid():
+    """The 128 (T, U) configurations, T slowest."""
+    T, U = np.meshgrid(T_VALUES, U_VALUES, indexing="ij")
+    return np.ascontiguousarray(T.reshape(-1)), np.ascontiguousarray(U.reshape(-1))
+
+
+def sample_instances(per_family: int, seed: int = 0):
+    """[(family, n)] with log-uniform sizes, `per_family` of each family."""
+    g = workloads.rng(DATASET_ID, 100 + int(seed))
+    out = []
+    for fam in FAMILIES:
+        lo, hi = SIZE_RANGE[fam]
+        n = np.floor(np.exp(g.uniform(np.log(lo), np.log(hi + 1), per_family))).astype(np.int64)
+        n = np.clip(n, lo, hi)
+        if fam == "matvec":
+            n = np.clip(np.round(n / 840.0).astype(np.int64) * 840, 1680, 32760)
+        out += [(fam, int(x)) for x in n]
+    return out
+
+
+def _lib():
+    return api.lib()
+
+
+def grid(fam: str, n: int, T: int, U: int, n_cu: int) -> int:
+    g = int(_lib().sa_rt_grid(FAMILY_ID[fam], n, T, U, n_cu))
+    if g < 1:
+        raise ValueError("(%s, n=%d, T=%d, U=%d) outside the family's domain" % (fam, n, T, U))
+    return g
+
+
+def trips(fam: str, n: int, T: int, U: int, G: int, n_loops: int):
+    out = []
+    for loop in range(n_loops):
+        t = int(_lib().sa_rt_trips(FAMILY_ID[fam], n, T, U, G, loop))
+        if t < 0:
+            raise ValueError("%s has no loop %d" % (fam, loop))
+        out.append(t)
+    return out
+
+
+def static_rows(instances, n_cu: int, kernels=None) -> dict:
+    """Static model inputs of every (instance, configuration) row."""
+    kernels = kernels or asm_features.runtime_kernels()
+    T, U = config_grid()
+    n_rows = len(instances) * N_CFG
+    cols = {f: np.zeros(n_rows, np.int64) for f in COUNT_FIELDS}
+    cols.update(family=np.zeros(n_rows, np.int32), n=np.zeros(n_rows, np.int64), block=np.zeros(n_rows, np.int32),
+                unroll=np.zeros(n_rows, np.int32), grid=np.zeros(n_rows, np.int32), regs=np.zeros(n_rows, np.int32),
+                lds=np.zeros(n_rows, np.int32), div=np.zeros(n_rows, np.float32))
+    r = 0
+    for fam, n in instances:
+        for t, u in zip(T, U):
+            km = kernels[(fam, int(u))]
+            G = grid(fam, n, int(t), int(u), n_cu)
+            tr = trips(fam, n, int(t), int(u), G, len(km.loops))
+            c = km.counts(tr)
+            for f in COUNT_FIELDS:
+                cols[f][r] = c[f]
+            cols["family"][r] = FAMILY_ID[fam]
+            cols["n"][r] = n
+            cols["block"][r] = t
+            cols["unroll"][r] = u
+            cols["grid"][r] = G
+            cols["regs"][r] = km.regs
+            cols["lds"][r] = km.lds
+            cols["div"][r] = km.divergence(tr)
+            r += 1
+    return cols
+
+
+def measure(instances, n_cu: int, device="cuda", warmup: int = 1, reps: int = 10, keep: int = 5, seed: int = 0,
+            log=None):
+    """Milliseconds [n_instances, 128]: the keep-th smallest of `reps` timed
+    launches after `warmup` untimed ones, per configuration."""
+    import torch
+
+    T, U = config_grid()
+    out = np.zeros((len(instances), N_CFG), np.float32)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(170108547 + int(seed))
+    L = _lib()
+    bufs = {}
+    # one set of buffers per family, sized for its largest instance
+    for fam in FAMILIES:
+        sizes = [n for f, n in instances if f == fam]
+        if not sizes:
+            continue
+        nmax = max(sizes)
+        fid = FAMILY_ID[fam]
+        b = []
+        for which in range(3):
+            m = int(L.sa_rt_buffer_floats(fid, nmax, which))
+            t = torch.randn(m, generator=gen, device=device) if m else None
+            b.append(t)
+        bufs[fam] = b
+    ms = np.zeros(N_CFG, np.float32)
+    t0 = time.time()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    for i, (fam, n) in enumerate(instances):
+        a, bb, c = bufs[fam]
+        p = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        st = L.sa_rt_measure(FAMILY_ID[fam], n, p(a), p(bb), p(c), T.ctypes.data_as(ctypes.c_void_p),
+                             U.ctypes.data_as(ctypes.c_void_p), N_CFG, n_cu, warmup, reps, keep,
+                             ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(stream))
+        if st != 0:
+            raise RuntimeError("sa_rt_measure: %s" % L.sa_rt_last_error().decode())
+        out[i] = ms
+        if log and (i + 1) % 50 == 0:
+            log("measured %d / %d instances, %.1f s" % (i + 1, len(instances), time.time() - t0))
+    return out
+
+
+def build(per_family: int, seed: int = 0, device="cuda", log=None) -> dict:
+    import torch
+
+    n_cu = torch.cuda.get_device_properties(device).multi_processor_count
+    inst = sample_instances(per_family, seed)
+    rows = static_rows(inst, n_cu)
+    ms = measure(inst, n_cu, device, seed=seed, log=log)
+    rows["ms"] = ms.reshape(-1)
+    rows["instance"] = np.repeat(np.arange(len(inst), dtype=np.int32), N_CFG)
+    rows["n_cu"] = np.array([n_cu])
+    return rows
+
+
+def save(path: str, data: dict):
+    np.savez_compressed(path, **data)
+
+
+def load(path: str) -> dict:
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--per-family", type=int, default=500)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)
+    t0 = time.time()
+    d = build(a.per_family, a.seed, log=log)
+    save(a.out, d)
+    print(json.dumps({"rows": int(d["ms"].size), "instances": int(d["instance"].max() + 1),
+                      "seconds": time.time() - t0}), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

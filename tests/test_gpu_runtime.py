@@ -1,0 +1,90 @@
+"""GPU tests of the measured kernel families and the timing harness: each
+family computes what it is documented to compute (checked against plain
+torch on the same inputs), timings are positive and follow the order
+statistic asked for, and a small dataset builds end to end."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1701_08547_amd import api, runtime_dataset as rd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def say(*a):
+    print("[gpu-runtime]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run_one(fam, n, T, U, a, b, c):
+    L = api.lib()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    Ts = np.array([T], np.int32)
+    Us = np.array([U], np.int32)
+    ms = np.zeros(1, np.float32)
+    p = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    st = L.sa_rt_measure(rd.FAMILY_ID[fam], n, p(a), p(b), p(c), Ts.ctypes.data_as(ctypes.c_void_p),
+                         Us.ctypes.data_as(ctypes.c_void_p), 1, n_cu, 0, 1, 1, ms.ctypes.data_as(ctypes.c_void_p),
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0, L.sa_rt_last_error()
+    torch.cuda.synchronize()
+    assert ms[0] > 0
+    return ms[0]
+
+
+@pytest.mark.parametrize("T,U", [(64, 1), (192, 3), (1024, 8), (320, 5)])
+def test_matvec_computes_y_plus_Ax(T, U):
+    n = 1680
+    g = torch.Generator(device="cuda").manual_seed(1)
+    A = torch.randn(n * n, device="cuda", generator=g)
+    x = torch.randn(n, device="cuda", generator=g)
+    y = torch.ones(n, device="cuda")
+    say("matvec", n, T, U)
+    run_one("matvec", n, T, U, A, x, y)
+    ref = 1.0 + (A.view(n, n).double().t() @ x.double())  # column-major A
+    assert torch.allclose(y.double(), ref, rtol=1e-4, atol=1e-3)
+
+
+@pytest.mark.parametrize("T,U", [(64, 1), (448, 7), (1024, 4)])
+def test_stencil_computes_5_point_sweep(T, U):
+    n = 515
+    g = torch.Generator(device="cuda").manual_seed(2)
+    a = torch.randn(n * n, device="cuda", generator=g)
+    c = torch.zeros(n * n, device="cuda")
+    say("stencil", n, T, U)
+    run_one("stencil", n, T, U, a, None, c)
+    A = a.view(n, n)
+    ref = 0.25 * (A[1:-1, :-2] + A[1:-1, 2:] + A[:-2, 1:-1] + A[2:, 1:-1]) - A[1:-1, 1:-1]
+    assert torch.allclose(c.view(n, n)[1:-1, 1:-1], ref, rtol=1e-5, atol=1e-5)
+    assert torch.all(c.view(n, n)[0] == 0) and torch.all(c.view(n, n)[:, -1] == 0)
+
+
+@pytest.mark.parametrize("T,U", [(64, 1), (960, 6), (1024, 8), (128, 2)])
+def test_reduce_computes_sum(T, U):
+    n = (1 << 20) + 12345
+    g = torch.Generator(device="cuda").manual_seed(3)
+    a = torch.randn(n, device="cuda", generator=g)
+    c = torch.zeros(1, device="cuda")
+    say("reduce", n, T, U)
+    run_one("reduce", n, T, U, a, None, c)
+    ref = a.double().sum()
+    assert abs(float(c[0]) - float(ref)) <= 1e-3 * float(a.double().abs().sum()) ** 0.5 + 1e-2
+
+
+def test_protocol_order_statistic_and_dataset():
+    inst = [("matvec", 1680), ("stencil", 600), ("reduce", 1 << 20)]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    say("dataset of", inst)
+    ms = rd.measure(inst, n_cu)
+    assert ms.shape == (3, rd.N_CFG) and np.all(np.isfinite(ms)) and np.all(ms > 0)
+    # keep = the minimum of the same number of launches is never above the 5th smallest
+    ms_min = rd.measure(inst[:1], n_cu, keep=1)
+    assert np.median(ms_min[0] / ms[0]) <= 1.0 + 1e-6
+    rows = rd.static_rows(inst, n_cu)
+    assert rows["n_fp"].size == 3 * rd.N_CFG and np.all(rows["grid"] >= 1)
