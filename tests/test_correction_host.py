@@ -1,0 +1,43 @@
+"""Host logic of the correction pipeline: ranking metrics against the
+oracle's definitions and scipy, residual targets, the held-out split."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_1701_08547_amd import correction
+
+
+def test_metrics_match_oracle_and_scipy():
+    stats = pytest.importorskip("scipy.stats")
+    g = np.random.default_rng(5)
+    for _ in range(30):
+        a = g.integers(0, 12, 128).astype(float)
+        t = np.exp(g.standard_normal(128))
+        assert correction.spearman(a, t) == pytest.approx(stats.spearmanr(a, t).correlation, abs=1e-12)
+        assert correction.spearman(a, t) == pytest.approx(omlp.spearman(a, t), abs=1e-12)
+        assert correction.regret(a, t) == omlp.top1_regret(a, t)
+    assert correction.regret(np.array([2.0, 1.0, 1.0]), np.array([3.0, 2.0, 1.0])) == 1.0  # tie -> lower index
+
+
+def test_residual_targets_remove_instance_medians():
+    ln_t = np.array([[1.0, 2.0, 3.0], [0.0, 0.0, 6.0]])
+    ln_s = np.array([[5.0, 5.0, 5.0], [1.0, 2.0, 3.0]])
+    r = correction.residual_targets(ln_t, ln_s)
+    assert np.allclose(r, [[-1.0, 0.0, 1.0], [1.0, 0.0, 5.0]])
+    # a plain key that already ranks perfectly up to scale leaves a zero residual
+    assert np.allclose(correction.residual_targets(ln_s * 1.0, ln_s), 0.0)
+
+
+def test_holdout_split_is_stratified_and_disjoint():
+    fam = np.repeat(np.arange(3), [50, 30, 20])
+    tr, ho = correction.holdout_split(fam, 0.1, 0)
+    assert np.intersect1d(tr, ho).size == 0 and tr.size + ho.size == 100
+    assert [int((fam[ho] == f).sum()) for f in range(3)] == [5, 3, 2]
+    tr2, ho2 = correction.holdout_split(fam, 0.1, 0)
+    assert np.array_equal(ho, ho2)
+
+
+def test_init_params_layout():
+    p = correction.init_params(0)
+    assert p["W1"].shape == (128, 32) and np.all(p["W1"][:, 24:] == 0)
+    assert np.abs(p["W2"]).max() <= 1 / np.sqrt(128)
