@@ -244,6 +244,9 @@ def regret_leg(per_family: int):
     return sur, {"instances": int(data["instance"].max()) + 1, "held_out": a["instances"],
                  "regret_plain": a["regret_plain"], "regret_corrected": a["regret_corrected"],
                  "spearman_plain": a["spearman_plain"], "spearman_corrected": a["spearman_corrected"],
+                 "paper_pruned_fraction": a.get("pruned_fraction"),
+                 "regret_paper_pruned_plain": a.get("regret_pruned_plain"),
+                 "regret_paper_pruned_best": a.get("regret_pruned_best"),
                  "seconds": time.perf_counter() - t0}
 
 

@@ -256,6 +256,28 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
 sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int64_t n_evals, int32_t k,
                   int32_t *idx, float *val, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * The paper's search-space reduction (Sec. III-C; pruning rates Sec. IV-C):
+ * T* = the block sizes, multiples of the wave size up to the thread limit,
+ * at which occupancy (Eqs. 1-5) is full when registers and LDS do not limit;
+ * a kernel whose intensity n_fp / max(1, n_ld + n_st) exceeds 4 keeps the
+ * upper half of T* (by thread count), any other the lower half; an odd-length
+ * T* drops its median.  kept uint64[n_variants] (8-byte aligned): bit j set
+ * when T = wave_size * (j + 1) is kept.  Asynchronous on `stream`.
+ */
+sa_status sa_suggest(const sa_arch *arch, const sa_variants *variants, int64_t n_variants, uint64_t *kept,
+                     void *stream);
+
+/* sa_score's pass with the top-k restricted to the reduced space: only
+ * evaluations whose block size is kept by sa_suggest's rule compete; the
+ * optional occupancy and score outputs cover every evaluation.  k in
+ * [1, SA_K_MAX]; at least one of topk_idx / topk_val.  Workspace as for
+ * sa_score. */
+sa_status sa_score_suggested(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
+                             int64_t n_variants, int64_t n_evals, float *score, int32_t *occ_waves, int32_t k,
+                             int32_t *topk_idx, float *topk_val, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
 /* The 24 features of every evaluation, feat float[n_evals][24] (features of
  * illegal evaluations are unspecified).  Asynchronous on `stream`. */
 sa_status sa_features(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,

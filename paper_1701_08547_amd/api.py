@@ -40,6 +40,7 @@ EXPORTED = (
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure",
+    "sa_suggest", "sa_score_suggested",
 )
 MLP_PARAMS = 20865
 MLP_FLAT = 20992
@@ -134,6 +135,11 @@ def lib():
             L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64, vp, vp, sz,
                                                   vp]
             L.sa_surrogate_train_step.restype = i32
+            L.sa_suggest.argtypes = [P(SaArch), P(SaVariants), i64, vp, vp]
+            L.sa_suggest.restype = i32
+            L.sa_score_suggested.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp,
+                                             vp, sz, vp]
+            L.sa_score_suggested.restype = i32
             L.sa_rt_last_error.restype = ctypes.c_char_p
             L.sa_rt_grid.argtypes = [i32, i64, i32, i32, i32]
             L.sa_rt_grid.restype = i64
@@ -316,6 +322,40 @@ def score(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: 
                           _ptr(o["idx"] if want_topk else None, torch.int32, "idx"),
                           _ptr(o["val"] if want_topk else None, torch.float32, "val"),
                           None if mlp is None else ctypes.byref(mlp.struct()), ws_ptr, ws_bytes, _stream(stream)))
+    return o
+
+
+def suggest(arch: dict, variants: dict, out=None, stream=None):
+    """The paper's reduced search space per variant (sa_suggest): int64
+    tensor whose bit j keeps the block size wave_size * (j + 1)."""
+    torch = _torch()
+    n_var = int(variants["n_fp"].shape[0])
+    if out is None:
+        out = torch.zeros(n_var, dtype=torch.int64, device=variants["n_fp"].device)
+    a = _arch_struct(arch)
+    _check(lib().sa_suggest(ctypes.byref(a), ctypes.byref(_variants_struct(variants)), n_var,
+                            _ptr(out, torch.int64, "kept"), _stream(stream)))
+    return out
+
+
+def score_suggested(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: bool = False,
+                    want_occ: bool = False, workspace: Workspace | None = None, stream=None) -> dict:
+    """Top-k by score within the paper's reduced search space (sa_score_suggested)."""
+    torch = _torch()
+    n_var, n_evals = _sizes(variants, configs)
+    dev = configs["seg"].device
+    o = {"occ": torch.empty(n_evals, dtype=torch.int32, device=dev) if want_occ else None,
+         "score": torch.empty(n_evals, dtype=torch.float32, device=dev) if want_score else None,
+         "idx": torch.empty((n_var, k), dtype=torch.int32, device=dev),
+         "val": torch.empty((n_var, k), dtype=torch.float32, device=dev)}
+    if workspace is None:
+        workspace = Workspace(workspace_bytes(n_var, n_evals, k), dev)
+    a = _arch_struct(arch)
+    _check(lib().sa_score_suggested(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
+                                    ctypes.byref(_configs_struct(configs)), n_var, n_evals,
+                                    _ptr(o["score"], torch.float32, "score"), _ptr(o["occ"], torch.int32, "occ"),
+                                    int(k), _ptr(o["idx"], torch.int32, "idx"), _ptr(o["val"], torch.float32, "val"),
+                                    workspace.ptr, workspace.nbytes, _stream(stream)))
     return o
 
 

@@ -14,7 +14,10 @@ evaluation (sa_surrogate_fwd).
 Evaluation per held-out instance (10 % of the instances of each family):
 top-1 regret t(argmin key) / min t - 1 (ties to the lower index) and the
 Spearman rank correlation of key and runtime, for the plain and the
-corrected key; means with bootstrap confidence intervals.
+corrected key; means with bootstrap confidence intervals.  Also the paper's
+own reduction of the space (T* and the intensity rule, sa_suggest): the
+fraction of configurations it removes and the regret of choosing within
+what it keeps.
 
 CLI (GPU): python -m paper_1701_08547_amd.correction --data runtime.npz \\
               --epochs 40 --out correction.npz --report correction.json
@@ -145,21 +148,37 @@ def corrected_keys(feat, sur):
     return feat[:, 22] + sur.forward(feat)
 
 
-def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, families: np.ndarray) -> dict:
+def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, families: np.ndarray,
+             pruned: np.ndarray | None = None) -> dict:
     """Regret and Spearman of the plain and corrected keys per held-out
-    instance ([n_inst, 128] arrays), overall and per family."""
+    instance ([n_inst, 128] arrays), overall and per family.  With `pruned`
+    (bool [n_inst, 128], the configurations the paper's reduction keeps): the
+    fraction of the space it removes and the regret of choosing within it
+    (the best kept configuration, and the plain / corrected argmin over it)."""
     rep = {}
+
+    def within(key, t, m):
+        if not m.any():
+            return np.nan
+        k = np.where(m, key, np.inf)
+        return float(t[int(np.argmin(k))] / t.min() - 1.0)
 
     def block(ids):
         rp = np.array([regret(ln_s[i], ms[i]) for i in ids])
         rc = np.array([regret(z[i], ms[i]) for i in ids])
         sp = np.array([spearman(ln_s[i], ms[i]) for i in ids])
         sc = np.array([spearman(z[i], ms[i]) for i in ids])
-        return {"instances": int(len(ids)),
-                "regret_plain": float(rp.mean()), "regret_plain_ci": bootstrap_ci(rp),
-                "regret_corrected": float(rc.mean()), "regret_corrected_ci": bootstrap_ci(rc),
-                "regret_diff_ci": bootstrap_ci(rp - rc),
-                "spearman_plain": float(sp.mean()), "spearman_corrected": float(sc.mean())}
+        out = {"instances": int(len(ids)),
+               "regret_plain": float(rp.mean()), "regret_plain_ci": bootstrap_ci(rp),
+               "regret_corrected": float(rc.mean()), "regret_corrected_ci": bootstrap_ci(rc),
+               "regret_diff_ci": bootstrap_ci(rp - rc),
+               "spearman_plain": float(sp.mean()), "spearman_corrected": float(sc.mean())}
+        if pruned is not None:
+            out["pruned_fraction"] = float(1.0 - pruned[ids].mean())
+            out["regret_pruned_best"] = float(np.nanmean([within(ms[i], ms[i], pruned[i]) for i in ids]))
+            out["regret_pruned_plain"] = float(np.nanmean([within(ln_s[i], ms[i], pruned[i]) for i in ids]))
+            out["regret_pruned_corrected"] = float(np.nanmean([within(z[i], ms[i], pruned[i]) for i in ids]))
+        return out
 
     rep["all"] = block(held)
     for f, name in enumerate(FAMILIES):
@@ -197,7 +216,12 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     torch.cuda.synchronize()
     train_s = time.time() - t0
     z = corrected_keys(feat, sur).cpu().numpy().astype(np.float64).reshape(n_inst, N_CFG)
-    rep = evaluate(ms, ln_s, z, held, families)
+    kept = api.suggest(arch, var).cpu().numpy().view(np.uint64)
+    ws = int(arch["wave_size"])
+    T = data["block"].astype(np.int64)
+    j = np.clip(T // ws - 1, 0, 63).astype(np.uint64)
+    pruned = ((T % ws == 0) & (((kept >> j) & np.uint64(1)) == 1)).reshape(n_inst, N_CFG)
+    rep = evaluate(ms, ln_s, z, held, families, pruned)
     rep["train"] = {"rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
                     "loss_first": losses[0], "loss_last": losses[-1],
                     "target_var": float(np.var(r.reshape(-1)[rows_tr]))}

@@ -347,6 +347,71 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   return SA_OK;
 }
 
+sa_status sa_suggest(const sa_arch *arch, const sa_variants *variants, int64_t n_variants, uint64_t *kept,
+                     void *stream) {
+  sa_status st;
+  if ((st = check_arch(arch)) != SA_OK) return st;
+  if (n_variants < 0) return fail(SA_ERR_ARG, "negative n_variants");
+  if (n_variants == 0) return SA_OK;
+  if ((st = check_variants(variants, n_variants)) != SA_OK) return st;
+  if (!kept) return fail(SA_ERR_ARG, "kept is NULL");
+  if (!aligned(kept, 8)) return fail(SA_ERR_ALIGN, "kept not 8-byte aligned");
+  sa::EvalLaunch L{};
+  L.arch = to_karch(arch);
+  L.var = {variants->n_fp, variants->n_int, variants->n_ld, variants->n_st, variants->n_br,
+           variants->n_bar, variants->n_reg, variants->lds_bytes, variants->div};
+  L.n_var = n_variants;
+  set_lds_layout(L);
+  hipError_t e = sa::launch_suggest(L, kept, (hipStream_t)stream);
+  return e == hipSuccess ? SA_OK : hip_fail(e, "sa_suggest_kernel launch");
+}
+
+sa_status sa_score_suggested(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
+                             int64_t n_variants, int64_t n_evals, float *score, int32_t *occ_waves, int32_t k,
+                             int32_t *topk_idx, float *topk_val, void *workspace, size_t workspace_bytes,
+                             void *stream) {
+  sa_status st;
+  if ((st = check_arch(arch)) != SA_OK) return st;
+  if ((st = check_sizes(n_variants, n_evals)) != SA_OK) return st;
+  if ((st = check_variants(variants, n_variants)) != SA_OK) return st;
+  if ((st = check_configs(configs, n_evals, true)) != SA_OK) return st;
+  if (!topk_idx && !topk_val) return fail(SA_ERR_ARG, "no top-k output");
+  if (k < 1 || k > SA_K_MAX) return fail(SA_ERR_ARG, "k = %d outside [1, %d]", k, SA_K_MAX);
+  const void *outs[] = {score, occ_waves, topk_idx, topk_val};
+  for (const void *p : outs)
+    if (p && !aligned(p, 4)) return fail(SA_ERR_ALIGN, "output not 4-byte aligned");
+  sa::EvalLaunch L{};
+  L.arch = to_karch(arch);
+  L.var = {variants->n_fp, variants->n_int, variants->n_ld, variants->n_st, variants->n_br,
+           variants->n_bar, variants->n_reg, variants->lds_bytes, variants->div};
+  L.cfg = {configs->seg, configs->block, configs->unroll, configs->regs, configs->grid};
+  L.n_var = n_variants;
+  L.n_evals = n_evals;
+  L.occ = occ_waves;
+  L.score = score;
+  L.topk_idx = topk_idx;
+  L.topk_val = topk_val;
+  L.k = k;
+  L.tile = pick_tile(n_evals);
+  L.n_tiles = ceil_div(n_evals, L.tile);
+  L.need_score = 1;
+  L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves, score}) ? 1 : 0;
+  set_lds_layout(L);
+  if (n_variants > 0) {
+    if ((st = bind_workspace(L, workspace, workspace_bytes)) != SA_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (n_evals > 0) {
+    hipError_t e = sa::launch_eval(L, sa::Mode::Suggest, configs->grid != nullptr, true, s);
+    if (e != hipSuccess) return hip_fail(e, "sa_eval_kernel launch");
+  }
+  if (n_variants > 0) {
+    hipError_t e = sa::launch_merge(L, s);
+    if (e != hipSuccess) return hip_fail(e, "sa_merge_kernel launch");
+  }
+  return SA_OK;
+}
+
 sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int64_t n_evals, int32_t k,
                   int32_t *idx, float *val, void *workspace, size_t workspace_bytes, void *stream) {
   sa_status st;

@@ -245,6 +245,7 @@ struct __align__(16) WaveLds {
 
 // Wave-uniform state of the piece being evaluated.
 struct Piece {
+  uint64_t kept;   // reduced search space: bit j keeps block size ws (j + 1)
   bool valid;      // variant counts in range
   int32_t gs;      // Eq. 5 bound for the variant's LDS
   float P, D;      // Eq. 6 per-variant sum, divergence weight 1 + d
@@ -438,6 +439,7 @@ template <Mode MODE>
 __device__ __forceinline__ void setup_piece(const EvalLaunch &L, Piece &pc, WaveLds &wl, int64_t v, int64_t s0,
                                             int lane) {
   const KArch &A = L.arch;
+  pc.kept = 0;
   pc.valid = true;
   pc.gs = 0;
   pc.P = 0.f;
@@ -445,7 +447,7 @@ __device__ __forceinline__ void setup_piece(const EvalLaunch &L, Piece &pc, Wave
   pc.s0 = s0;
   pc.a4 = wl.a4;
   pc.a5 = wl.a5;
-  if constexpr (MODE == Mode::Model) {
+  if constexpr (MODE != Mode::Keys) {
     const int32_t nfp = L.var.n_fp[v], nint = L.var.n_int[v], nld = L.var.n_ld[v], nst = L.var.n_st[v];
     const int32_t nbr = L.var.n_br[v], nbar = L.var.n_bar[v];
     const int32_t nreg = L.var.n_reg ? L.var.n_reg[v] : 0;
@@ -481,6 +483,45 @@ __device__ __forceinline__ void setup_piece(const EvalLaunch &L, Piece &pc, Wave
     if (lane < A.nw) wl.a5[lane + 1] = A.csync * (float)(nbar * (lane + 1));
     wave_lds_sync();
   }
+}
+
+
+// ---------------------------------------------------------------- reduced search space
+
+// Sec. III-C / IV-C: T* = the block sizes (multiples of the wave size) whose
+// occupancy is full when registers and LDS do not limit; bit j of the result
+// stands for T = ws (j + 1).  Read from row 0 (no register limit) of the
+// workgroup's occupancy table.
+__device__ __forceinline__ uint64_t full_occupancy_mask(const KArch &A, const uint8_t *tab_b) {
+  uint64_t m = 0;
+  for (int wb = 1; wb <= A.nw; ++wb)
+    if ((int32_t)tab_b[wb] * wb == A.max_waves) m |= 1ull << (wb - 1);
+  return m;
+}
+
+// The paper's rule: keep the upper half of T* (by thread count) when the
+// kernel's intensity n_fp / max(1, n_ld + n_st) exceeds 4, else the lower
+// half; an odd-length T* drops its median.  The comparison is made on the
+// integers (n_fp > 4 max(1, m)), which is exact.
+__device__ __forceinline__ uint64_t kept_mask(uint64_t full, int nw, int32_t nfp, int32_t nld, int32_t nst) {
+  const int32_t mem = nld + nst;
+  const bool upper = nfp > 4 * (mem > 1 ? mem : 1);
+  const int n = __popcll(full), h = n / 2;
+  uint64_t kept = 0;
+  int seen = 0;
+  for (int j = 0; j < nw; ++j) {
+    if ((full >> j) & 1ull) {
+      if (upper ? seen >= n - h : seen < h) kept |= 1ull << j;
+      ++seen;
+    }
+  }
+  return kept;
+}
+
+// Whether block size T lies in the kept set.
+__device__ __forceinline__ bool in_kept(uint64_t kept, const KArch &A, int32_t T) {
+  const uint32_t j = ((uint32_t)T >> A.ws_shift) - 1u;
+  return ((T & (A.ws - 1)) == 0) & (j < 64u) & (((kept >> (j & 63u)) & 1ull) != 0);
 }
 
 }  // namespace

@@ -33,6 +33,41 @@
 namespace sa {
 namespace {
 
+// Unconditional stores of one lane's N consecutive 4-byte values at byte
+// offset `off` of a buffer resource.  An output that was not asked for gets
+// a resource with no records, whose stores the hardware drops; the stores
+// stay unconditional in the program, so the compiler knows how many memory
+// operations follow each prefetch and can wait for the prefetch alone
+// (optional stores behind a branch would make it wait for everything).
+typedef uint32_t v2u32_t __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u32_t __attribute__((ext_vector_type(4)));
+constexpr int kBufFlags = 0x00020000;  // raw 32-bit buffer, gfx9 word 3
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(void *p, int64_t byte0, int bytes) {
+  // the offset is wave-uniform; saying so keeps the resource in scalar
+  // registers (a possibly divergent resource costs a per-store loop)
+  const uint64_t a = p ? (uint64_t)p + (uint64_t)byte0 : 0ull;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0, p ? bytes : 0, kBufFlags);
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void buf_store(const T (&x)[N], __amdgpu_buffer_rsrc_t r, int off) {
+  constexpr int aux = SA_NT_STORE ? 2 : 0;  // non-temporal
+  uint32_t u[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = __builtin_bit_cast(uint32_t, x[i]);
+  if constexpr (N == 4) {
+    __builtin_amdgcn_raw_buffer_store_b128(v4u32_t{u[0], u[1], u[2], u[3]}, r, off, 0, aux);
+  } else if constexpr (N == 2) {
+    __builtin_amdgcn_raw_buffer_store_b64(v2u32_t{u[0], u[1]}, r, off, 0, aux);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) __builtin_amdgcn_raw_buffer_store_b32(u[i], r, off + 4 * i, 0, aux);
+  }
+}
+
 // Streams one piece [e, pe) of one segment.  ITEMS consecutive evaluations
 // per lane per chunk (chunk = 64 ITEMS evaluations), one chunk of loads in
 // flight ahead of the one being evaluated.
@@ -55,7 +90,7 @@ struct Evaluator {
     for (int i = 0; i < 4; ++i) {
       const int j = lane + 64 * i;
       const bool in = j < rem;
-      if constexpr (MODE == Mode::Model) {
+      if constexpr (MODE != Mode::Keys) {
         Tv[i] = in ? L.cfg.block[base + j] : 0;
         Uv[i] = in ? L.cfg.unroll[base + j] : 0;
         Rv[i] = in ? L.cfg.regs[base + j] : 0;
@@ -73,7 +108,7 @@ struct Evaluator {
       const int64_t e = base + j;
       float sc;
       bool ok;
-      if constexpr (MODE == Mode::Model) {
+      if constexpr (MODE != Mode::Keys) {
         int32_t W;
         eval_cfg<HAS_GRID>(L.arch, tb, pc, Tv[i], Uv[i], Rv[i], Gv[i], in, L.need_score, W, sc);
         if (L.occ && in) L.occ[e] = W;
@@ -85,6 +120,7 @@ struct Evaluator {
       }
       const uint32_t kk = order_key(sc);
       cand[i] = ok && kk <= sel.theta;
+      if constexpr (MODE == Mode::Suggest) cand[i] = cand[i] && in_kept(pc.kept, L.arch, Tv[i]);
       key[i] = ((uint64_t)kk << 32) | (uint32_t)(e - pc.s0);
     }
     if constexpr (TOPK) offer<4>(sel, cand, key);
@@ -98,7 +134,7 @@ struct Evaluator {
   __device__ __forceinline__ Cols load_chunk(int64_t base) const {
     Cols c;
     const int64_t o = base + ITEMS * lane;
-    if constexpr (MODE == Mode::Model) {
+    if constexpr (MODE != Mode::Keys) {
       c.T = *(const IVec<ITEMS> *)(L.cfg.block + o);
       c.U = *(const IVec<ITEMS> *)(L.cfg.unroll + o);
       c.R = *(const IVec<ITEMS> *)(L.cfg.regs + o);
@@ -119,14 +155,15 @@ struct Evaluator {
     float sc[ITEMS];
     int32_t W[ITEMS];
     bool ok[ITEMS];
-    if constexpr (MODE == Mode::Model) {
+    if constexpr (MODE != Mode::Keys) {
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         eval_cfg<HAS_GRID>(L.arch, tb, pc, c.T.v[i], c.U.v[i], c.R.v[i], c.G.v[i], true, L.need_score, W[i], sc[i]);
         ok[i] = W[i] > 0;
       }
-      if (L.occ) store_n<ITEMS>(L.occ + o, W);
-      if (L.score) store_n<ITEMS>(L.score + o, sc);
+      const int off = 4 * ITEMS * lane;
+      buf_store<ITEMS>(W, out_rsrc(L.occ, 4 * base, 4 * kC), off);
+      buf_store<ITEMS>(sc, out_rsrc(L.score, 4 * base, 4 * kC), off);
     } else {
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
@@ -142,8 +179,9 @@ struct Evaluator {
       for (int i = 0; i < ITEMS; ++i) {
         // model scores are +0 .. +inf: the key is the bit pattern with the
         // sign bit set, and +inf's key lies above every threshold
-        const uint32_t kk = MODE == Mode::Model ? (__float_as_uint(sc[i]) | 0x80000000u) : order_key(sc[i]);
-        cand[i] = MODE == Mode::Model ? kk <= sel.theta : (ok[i] && kk <= sel.theta);
+        const uint32_t kk = MODE != Mode::Keys ? (__float_as_uint(sc[i]) | 0x80000000u) : order_key(sc[i]);
+        cand[i] = MODE != Mode::Keys ? kk <= sel.theta : (ok[i] && kk <= sel.theta);
+        if constexpr (MODE == Mode::Suggest) cand[i] = cand[i] && in_kept(pc.kept, L.arch, c.T.v[i]);
         key[i] = ((uint64_t)kk << 32) | (li + (uint32_t)i);
       }
       offer<ITEMS>(sel, cand, key);
@@ -161,17 +199,40 @@ struct Evaluator {
       body = a0;
       const int64_t nfull = (pe - a0) / kC;
       if (nfull > 0) {
-        Cols cur = load_chunk(a0);
-        for (int64_t it = 0; it < nfull; ++it) {
+        // Unrolled by two so that the chunk in flight and the chunk being
+        // evaluated alternate between two register sets: a loop-carried copy
+        // of the prefetched registers would make every iteration wait for all
+        // outstanding memory operations, this chunk's stores included.  The
+        // prefetches are unconditional (a conditional load would make the
+        // compiler wait for it before evaluating); past the last chunk they
+        // re-read one that is still cached.
+        Cols a = load_chunk(a0);
+        if constexpr (MODE != Mode::Keys) {
+          // two dropped stores: the loop is entered with the same memory
+          // operations behind the first prefetch as every later iteration
+          // (a chunk's two output stores), so its waits stay exact
+          const int32_t z[ITEMS] = {};
+          buf_store<ITEMS>(z, out_rsrc(nullptr, 0, 0), 0);
+          buf_store<ITEMS>(z, out_rsrc(nullptr, 0, 0), 4 * ITEMS * 64);
+        }
+        int64_t it = 0;
+        for (; it + 2 <= nfull; it += 2) {
           const int64_t base = a0 + it * kC;
           if constexpr (TOPK) make_room(sel, kC, L.k, lane);
-          // the prefetch is unconditional (a conditional load would make the
-          // compiler wait for every load before evaluating cur); past the
-          // last chunk it re-reads the current one, which is still cached
-          const bool more = it + 1 < nfull;
-          const Cols nxt = load_chunk(more ? base + kC : base);
-          chunk(cur, base);
-          cur = nxt;
+          const Cols b = load_chunk(base + kC);
+          // keep the scheduler from hoisting this chunk's first uses above
+          // the prefetch: the wait for the current data can then leave the
+          // prefetch (and any stores before it) in flight
+          __builtin_amdgcn_sched_barrier(0);
+          chunk(a, base);
+          if constexpr (TOPK) make_room(sel, kC, L.k, lane);
+          a = load_chunk(it + 2 < nfull ? base + 2 * kC : base + kC);
+          __builtin_amdgcn_sched_barrier(0);
+          chunk(b, base + kC);
+        }
+        if (it < nfull) {
+          if constexpr (TOPK) make_room(sel, kC, L.k, lane);
+          chunk(a, a0 + it * kC);
         }
         body = a0 + nfull * kC;
       }
@@ -197,7 +258,7 @@ void sa_eval_kernel(EvalLaunch L) {
   const int lane = lane_id();
   const int w = tid / kWaveSize;
   (void)A;
-  if constexpr (MODE == Mode::Model) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, kBlockThreads);
+  if constexpr (MODE != Mode::Keys) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, kBlockThreads);
   const uint8_t *tab_b = dyn_lds;
 
   const int64_t wt = (int64_t)blockIdx.x * kWavesPerBlock + w;
@@ -225,6 +286,8 @@ void sa_eval_kernel(EvalLaunch L) {
 
     Piece pc;
     setup_piece<MODE>(L, pc, wl[w], v, s0, lane);
+    if constexpr (MODE == Mode::Suggest)
+      pc.kept = kept_mask(full_occupancy_mask(A, tab_b), A.nw, L.var.n_fp[v], L.var.n_ld[v], L.var.n_st[v]);
 
     if constexpr (TOPK) {
       sel.count = 0;
@@ -312,7 +375,7 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = tid / kWaveSize;
-  if constexpr (MODE == Mode::Model) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, 64 * WPB);
+  if constexpr (MODE != Mode::Keys) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, 64 * WPB);
   const Tables tb{dyn_lds, tab_rcap};
   const int64_t n_evals = L.n_evals;
   const int64_t *seg = L.cfg.seg;
@@ -425,7 +488,7 @@ __global__ __launch_bounds__(kBlockThreads) void sa_split_merge_kernel(EvalLaunc
 template <Mode M, bool G, bool K, int I, int WPB>
 hipError_t launch_plan_one(const EvalLaunch &L, const PlanDev &P, int n_cu, hipStream_t stream) {
   if (P.n_items == 0) return hipSuccess;
-  const size_t dyn = M == Mode::Model ? (size_t)L.dyn_lds_bytes : 0;
+  const size_t dyn = M != Mode::Keys ? (size_t)L.dyn_lds_bytes : 0;
   static thread_local int resident = -1;  // workgroups per CU for this instantiation
   static thread_local size_t resident_dyn = (size_t)-1;
   if (resident < 0 || resident_dyn != dyn) {
@@ -458,7 +521,7 @@ template <Mode M, bool G, bool K>
 hipError_t launch_one(const EvalLaunch &L, hipStream_t stream) {
   const int64_t blocks = (L.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
-  const size_t dyn = M == Mode::Model ? (size_t)L.dyn_lds_bytes : 0;
+  const size_t dyn = M != Mode::Keys ? (size_t)L.dyn_lds_bytes : 0;
   hipLaunchKernelGGL((sa_eval_kernel<M, G, K>), dim3((uint32_t)blocks), dim3(kBlockThreads), dyn, stream, L);
   return hipGetLastError();
 }
@@ -466,6 +529,10 @@ hipError_t launch_one(const EvalLaunch &L, hipStream_t stream) {
 }  // namespace
 
 hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream) {
+  if (mode == Mode::Suggest) {
+    if (!topk) return hipErrorInvalidValue;
+    return has_grid ? launch_one<Mode::Suggest, true, true>(L, stream) : launch_one<Mode::Suggest, false, true>(L, stream);
+  }
   if (mode == Mode::Keys) {
     return topk ? launch_one<Mode::Keys, false, true>(L, stream) : hipErrorInvalidValue;
   }
@@ -493,6 +560,31 @@ hipError_t launch_split_merge(const EvalLaunch &L, const PlanDev &P, hipStream_t
   int64_t blocks = (P.n_splits + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(sa_split_merge_kernel, dim3((uint32_t)blocks), dim3(kBlockThreads), 0, stream, L, P);
+  return hipGetLastError();
+}
+
+namespace {
+// Per variant, the block sizes the paper's reduction keeps (bit j = T of
+// ws (j + 1) threads).
+__global__ __launch_bounds__(kBlockThreads) void sa_suggest_kernel(EvalLaunch L, uint64_t *kept) {
+  extern __shared__ __align__(16) uint8_t dyn_lds[];
+  __shared__ float tab_rcap[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 1];
+  __shared__ uint8_t tab_blim[kMaxWB + 1];
+  build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, threadIdx.x, kBlockThreads);
+  const uint64_t full = full_occupancy_mask(L.arch, dyn_lds);
+  for (int64_t v = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; v < L.n_var;
+       v += (int64_t)gridDim.x * kBlockThreads)
+    kept[v] = kept_mask(full, L.arch.nw, L.var.n_fp[v], L.var.n_ld[v], L.var.n_st[v]);
+}
+}  // namespace
+
+hipError_t launch_suggest(const EvalLaunch &L, uint64_t *kept, hipStream_t stream) {
+  if (L.n_var == 0) return hipSuccess;
+  int64_t blocks = (L.n_var + kBlockThreads - 1) / kBlockThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(sa_suggest_kernel, dim3((uint32_t)blocks), dim3(kBlockThreads), (size_t)L.dyn_lds_bytes, stream,
+                     L, kept);
   return hipGetLastError();
 }
 

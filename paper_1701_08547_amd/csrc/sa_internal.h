@@ -63,7 +63,9 @@ struct EvalLaunch {
   int32_t dyn_lds_bytes;
 };
 
-enum class Mode { Model, Keys };
+// Model: score the configurations; Keys: select over given keys; Suggest:
+// score, selecting only within the paper's reduced search space.
+enum class Mode { Model, Keys, Suggest };
 
 // A plan cuts a CSR batch into workgroup items.  kind 0: whole segments
 // [v0, v1) per wave.  kind 1: one segment's range split into one part per
@@ -137,6 +139,7 @@ struct AdamArgs {
 };
 
 hipError_t launch_features(const EvalLaunch &L, float *feat, hipStream_t stream);
+hipError_t launch_suggest(const EvalLaunch &L, uint64_t *kept, hipStream_t stream);
 hipError_t launch_corrected(const EvalLaunch &L, const MlpDev &M, bool has_grid, hipStream_t stream);
 hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream);
 int64_t train_slabs(int64_t n);

@@ -154,3 +154,20 @@ def test_no_device_is_reported(L):
     with pytest.raises(api.SAError) as e:
         api.arch_default(0)
     assert e.value.status == -3
+
+
+def test_suggest_argument_errors(L):
+    a = api.SaArch()
+    assert L.sa_arch_gfx950(ctypes.byref(a)) == 0
+    v = api.SaVariants(*([8] * 9))
+    assert L.sa_suggest(ctypes.byref(a), ctypes.byref(v), 5, None, None) == -1
+    assert L.sa_suggest(ctypes.byref(a), ctypes.byref(v), 5, ctypes.c_void_p(12), None) == -2
+    assert L.sa_suggest(ctypes.byref(a), ctypes.byref(v), -1, ctypes.c_void_p(16), None) == -1
+    assert L.sa_suggest(ctypes.byref(a), ctypes.byref(v), 0, None, None) == 0
+    c = api.SaConfigs(8, 8, 8, 8, None)
+    # no top-k output / k out of range
+    assert L.sa_score_suggested(ctypes.byref(a), ctypes.byref(v), ctypes.byref(c), 1, 1, None, None, 8, None, None,
+                                None, 0, None) == -1
+    assert L.sa_score_suggested(ctypes.byref(a), ctypes.byref(v), ctypes.byref(c), 1, 1, None, None, 0,
+                                ctypes.c_void_p(16), None, None, 0, None) == -1
+
