@@ -81,11 +81,12 @@ typedef int32_t sa_status;
  * R outside [0, max_vgprs_per_thread] or S outside [0, max_lds_per_block].
  *
  * Supported ranges (sa_arch_validate): wave_size a power of two in [2, 1024];
- * max_threads_per_block in [1, 65536]; ceil(max_threads_per_block /
- * wave_size) <= 64; max_waves_per_cu in [1, 64]; simd_per_cu in
- * [1, max_waves_per_cu]; max_blocks_per_cu >= 1; vgpr_granule a power of two with
- * (ceil(max_vgprs_per_thread / vgpr_granule) + 1) x
- * (ceil(max_threads_per_block / wave_size) + 1) <= 16384;
+ * max_threads_per_block in [1, 65536], a multiple of wave_size, with
+ * max_threads_per_block / wave_size <= 64; max_waves_per_cu in [1, 64];
+ * simd_per_cu in [1, max_waves_per_cu]; max_blocks_per_cu >= 1; vgpr_granule
+ * a power of two dividing max_vgprs_per_thread, with
+ * (max_vgprs_per_thread / vgpr_granule + 2) x
+ * (max_threads_per_block / wave_size + 2) <= 16384;
  * vgprs_per_simd_lane in [1, 65536]; lds_per_cu in [1, 2^24]; lds_granule
  * >= 1; max_lds_per_block in [0, 2^24]; n_cu in [1, 2048]; w_sat in
  * [1, 4096]; max_unroll in [1, 64]; max_grid in [1, 2^18]; every cpi_*

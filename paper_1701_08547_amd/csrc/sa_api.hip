@@ -64,12 +64,18 @@ sa_status check_arch(const sa_arch *a) {
 #undef SA_RANGE
   if (!pow2(a->wave_size)) return fail(SA_ERR_UNSUPPORTED, "wave_size %d is not a power of two", a->wave_size);
   if (!pow2(a->vgpr_granule)) return fail(SA_ERR_UNSUPPORTED, "vgpr_granule %d is not a power of two", a->vgpr_granule);
+  if (a->max_threads_per_block % a->wave_size)
+    return fail(SA_ERR_UNSUPPORTED, "max_threads_per_block %d is not a multiple of wave_size %d",
+                a->max_threads_per_block, a->wave_size);
+  if (a->max_vgprs_per_thread % a->vgpr_granule)
+    return fail(SA_ERR_UNSUPPORTED, "max_vgprs_per_thread %d is not a multiple of vgpr_granule %d",
+                a->max_vgprs_per_thread, a->vgpr_granule);
   const int64_t nw = ceil_div(a->max_threads_per_block, a->wave_size);
   const int64_t nr = ceil_div(a->max_vgprs_per_thread, a->vgpr_granule);
   if (nw > sa::kMaxWB) return fail(SA_ERR_UNSUPPORTED, "ceil(max_threads_per_block / wave_size) = %lld > %d", (long long)nw, sa::kMaxWB);
-  if ((nr + 1) * (nw + 1) > sa::kTabBMax)
-    return fail(SA_ERR_UNSUPPORTED, "occupancy table (%lld x %lld) exceeds %d entries", (long long)(nr + 1),
-                (long long)(nw + 1), sa::kTabBMax);
+  if ((nr + 2) * (nw + 2) > sa::kTabBMax)
+    return fail(SA_ERR_UNSUPPORTED, "occupancy table (%lld x %lld) exceeds %d entries", (long long)(nr + 2),
+                (long long)(nw + 2), sa::kTabBMax);
   const float c[6] = {a->cpi_fp, a->cpi_int, a->cpi_mem, a->cpi_ctrl, a->cpi_sync, a->cpi_reg};
   for (float x : c)
     if (!(x >= 0.0f) || !isfinite(x)) return fail(SA_ERR_UNSUPPORTED, "cpi weights must be finite and >= 0");
@@ -116,9 +122,9 @@ int32_t pick_tile(int64_t n_evals) {
 // Dynamic LDS of the evaluation kernel: occupancy table, then the per-granule
 // wave counts, each rounded to 16 bytes.
 void set_lds_layout(sa::EvalLaunch &L) {
-  const int32_t tab = (L.arch.nr + 1) * (L.arch.nw + 1);
+  const int32_t tab = (L.arch.nr + 2) * (L.arch.nw + 2);
   L.tab_wtot_off = (tab + 15) & ~15;
-  L.dyn_lds_bytes = L.tab_wtot_off + (((L.arch.nr + 1) + 15) & ~15);
+  L.dyn_lds_bytes = L.tab_wtot_off + (((L.arch.nr + 2) + 15) & ~15);
 }
 
 bool all16(std::initializer_list<const void *> ps) {

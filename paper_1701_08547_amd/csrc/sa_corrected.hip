@@ -24,8 +24,8 @@ template <bool HAS_GRID>
 __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunch L, MlpDev M) {
   extern __shared__ __align__(16) uint8_t dyn_lds[];
   __shared__ float tab_rcap[kMaxWB + 1];
-  __shared__ uint32_t tab_mwb[kMaxWB + 1];
-  __shared__ uint8_t tab_blim[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 2];
+  __shared__ uint8_t tab_blim[kMaxWB + 2];
   __shared__ MlpLdsT s;
   __shared__ WaveLds wl[kCorrWaves];
   __shared__ __align__(16) uint16_t X[kCorrWaves][64 * kLdXT];

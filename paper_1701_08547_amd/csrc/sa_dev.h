@@ -113,16 +113,14 @@ __device__ int64_t find_segment(const int64_t *seg, int64_t n_var, int64_t n_eva
   return lo;
 }
 
-// Floor division a / b for 0 <= a < 2^21, 1 <= b < 2^21, given rcp ~ 1/b to
-// within a few ulp: the float estimate is within 1 of the quotient, one
-// correction step each way makes it exact.
-__device__ __forceinline__ int32_t udiv_rcp(int32_t a, int32_t b, float rcp) {
-  int32_t q = (int32_t)((float)a * rcp);
-  int32_t r = a - (int32_t)__umul24((uint32_t)q, (uint32_t)b);
-  q = (r < 0) ? q - 1 : q;
-  r = (r < 0) ? r + b : r;
-  q = (r >= b) ? q + 1 : q;
-  return q;
+// Floor division a / b for 0 <= a < 2^19, 1 <= b <= 2^17, given r = 1/b
+// rounded to binary32 and then raised by three units in the last place.  The
+// binary32 estimate a r is then above a/b by a factor in (1, 1 + 2^-21], i.e.
+// by less than 1/4: its integer part is the quotient or one more, and one
+// test makes it exact.
+__device__ __forceinline__ int32_t udiv_up(int32_t a, int32_t b, float r) {
+  const int32_t q = (int32_t)((float)a * r);
+  return q - (int32_t)(__umul24((uint32_t)q, (uint32_t)b) > (uint32_t)a);
 }
 
 // ---------------------------------------------------------------- selection
@@ -239,7 +237,7 @@ __device__ __forceinline__ void write_final(uint64_t mine, int k, int lane, int6
 
 struct __align__(16) WaveLds {
   float a4[kMaxUnroll];  // (c_ctrl n_br) / U for U = 1 .. max_unroll
-  float a5[kMaxWB + 1];  // c_sync (n_bar W_B)    for W_B = 1 .. nw
+  float a5[kMaxWB + 2];  // c_sync (n_bar W_B)    for W_B = 1 .. nw (nw + 1: unused)
   uint64_t cand[kCandCap];
 };
 
@@ -255,7 +253,7 @@ struct Piece {
 
 struct Tables {
   const uint8_t *tab_b;  // [rg][W_B] -> min(G_W, G_R)
-  const float *rcap;     // [B] -> 1 / (n_cu B)
+  const float *rcap;     // [B] -> 1 / (n_cu B), raised 3 ulp (udiv_up)
 };
 
 // One configuration: W* (0 if illegal) and the binary32 score (+inf if
@@ -264,18 +262,20 @@ struct Tables {
 template <bool HAS_GRID>
 __device__ __forceinline__ void eval_cfg(const KArch &A, const Tables &tb, const Piece &pc, int32_t T, int32_t U,
                                          int32_t R, int32_t G, bool in, bool need_score, int32_t &W, float &sc) {
-  // bitwise '&' keeps the legality test free of branches
-  bool ok = in & pc.valid & ((uint32_t)(T - 1) < (uint32_t)A.max_threads) &
-            ((uint32_t)(U - 1) < (uint32_t)A.max_unroll) & ((uint32_t)R <= (uint32_t)A.max_vgprs);
+  // Block sizes and register counts outside their limits (negative ones
+  // included, as unsigned) are clamped one past the limit, which lands in the
+  // table's zero column (W_B = nw + 1) or zero row (granules = nr + 1): the
+  // thread and register limits are multiples of the wave size and granule.
+  const uint32_t Tc = min((uint32_t)T, (uint32_t)A.max_threads + 1u);
+  const uint32_t Rc = min((uint32_t)R, (uint32_t)A.max_vgprs + 1u);
+  // bitwise '&' keeps the remaining legality test free of branches
+  bool ok = in & pc.valid & ((uint32_t)(U - 1) < (uint32_t)A.max_unroll);
   if (HAS_GRID) ok = ok & ((uint32_t)(G - 1) < (uint32_t)A.max_grid);
-  // only the table indices need sanitising; G of an illegal lane is discarded
-  T = ok ? T : 1;
-  U = ok ? U : 1;
-  R = ok ? R : 0;
+  U = ok ? U : 1;  // table index; G of an illegal lane is discarded
   // Eqs. 1-5: waves per block, register granules, bound table, LDS bound
-  const int32_t WB = (T + A.ws - 1) >> A.ws_shift;
-  const int32_t rg = (R + (1 << A.gran_shift) - 1) >> A.gran_shift;
-  int32_t B = tb.tab_b[__umul24(rg, A.nw + 1) + WB];
+  const int32_t WB = (int32_t)((Tc + (uint32_t)A.ws - 1u) >> A.ws_shift);
+  const int32_t rg = (int32_t)((Rc + (1u << A.gran_shift) - 1u) >> A.gran_shift);
+  int32_t B = tb.tab_b[__umul24(rg, A.nw + 2) + WB];
   B = B < pc.gs ? B : pc.gs;
   B = ok ? B : 0;
   W = __umul24(B, WB);
@@ -290,7 +290,7 @@ __device__ __forceinline__ void eval_cfg(const KArch &A, const Tables &tb, const
     int32_t num, den;
     if (HAS_GRID) {
       const int32_t cap = __umul24(A.n_cu, B);
-      const int32_t rounds = udiv_rcp(G + cap - 1, cap, tb.rcap[B]);
+      const int32_t rounds = udiv_up(G + cap - 1, cap, tb.rcap[B]);
       num = __umul24(__umul24(rounds, cap), hide);
       den = __umul24(G, x);
     } else {
@@ -325,7 +325,7 @@ __device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, co
   R = ok ? R : 0;
   const int32_t WB = (T + A.ws - 1) >> A.ws_shift;
   const int32_t rg = (R + (1 << A.gran_shift) - 1) >> A.gran_shift;
-  int32_t B = tb.tab_b[__umul24(rg, A.nw + 1) + WB];
+  int32_t B = tb.tab_b[__umul24(rg, A.nw + 2) + WB];
   B = B < pc.gs ? B : pc.gs;
   B = ok ? B : 0;
   const int32_t W = __umul24(B, WB);
@@ -344,7 +344,7 @@ __device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, co
   int32_t num, den;
   if (HAS_GRID) {
     const int32_t cap = __umul24(A.n_cu, B);
-    const int32_t rounds = udiv_rcp(G + cap - 1, cap, tb.rcap[B]);
+    const int32_t rounds = udiv_up(G + cap - 1, cap, tb.rcap[B]);
     num = __umul24(__umul24(rounds, cap), hide);
     den = __umul24(G, x);
   } else {
@@ -396,31 +396,37 @@ __device__ __forceinline__ void store_n(float *p, const float (&x)[N]) {
 __device__ void build_tables(const EvalLaunch &L, uint8_t *dyn_lds, float *tab_rcap, uint32_t *tab_mwb,
                              uint8_t *tab_blim, int tid, int nthreads) {
   const KArch &A = L.arch;
-  const int row = A.nw + 1;
+  const int row = A.nw + 2;
   uint8_t *tab_b = dyn_lds;
   uint8_t *tab_wtot = dyn_lds + L.tab_wtot_off;
   // waves the register file admits per register-granule count (Eq. 4 plain
-  // reading), all slots when no registers are named
+  // reading), all slots when no registers are named; granule count nr + 1
+  // stands for every illegal register count and admits none
   const int slots = A.max_waves / A.simd;
-  for (int rg = tid; rg <= A.nr; rg += nthreads) {
+  for (int rg = tid; rg <= A.nr + 1; rg += nthreads) {
     int wtot = A.max_waves;
-    if (rg > 0) {
+    if (rg > A.nr) {
+      wtot = 0;
+    } else if (rg > 0) {
       const int per_simd = A.vgprs / (rg * A.vgpr_gran);
       wtot = A.simd * (per_simd < slots ? per_simd : slots);
     }
     tab_wtot[rg] = (uint8_t)wtot;
   }
-  // Eq. 3 block slots, and ceil(2^16 / W_B) for exact small divisions
-  for (int wb = tid; wb <= A.nw; wb += nthreads) {
+  // Eq. 3 block slots, and ceil(2^16 / W_B) for exact small divisions; W_B =
+  // nw + 1 stands for every illegal block size and admits no block
+  for (int wb = tid; wb <= A.nw + 1; wb += nthreads) {
     tab_mwb[wb] = wb > 0 ? (65536u + (uint32_t)wb - 1u) / (uint32_t)wb : 0u;
-    const int blim = (wb == 1 && A.exempt) ? 255 : (A.max_blocks < 255 ? A.max_blocks : 255);
-    tab_blim[wb] = (uint8_t)blim;
+    int blim = (wb == 1 && A.exempt) ? 255 : (A.max_blocks < 255 ? A.max_blocks : 255);
+    tab_blim[wb] = (uint8_t)(wb > A.nw ? 0 : blim);
   }
-  for (int i = tid; i <= A.max_waves; i += nthreads) tab_rcap[i] = i > 0 ? 1.0f / (float)(A.n_cu * i) : 0.0f;
+  // 1 / (n_cu B) raised by three ulp for udiv_up
+  for (int i = tid; i <= A.max_waves; i += nthreads)
+    tab_rcap[i] = i > 0 ? __uint_as_float(__float_as_uint(1.0f / (float)(A.n_cu * i)) + 3u) : 0.0f;
   __syncthreads();
   // min(G_W, G_R) = min(B_lim, floor(wtot / W_B)): the register bound never
   // exceeds floor(max_waves / W_B), the wave-slot part of Eq. 3
-  const int n_tab = (A.nr + 1) * row;
+  const int n_tab = (A.nr + 2) * row;
   for (int i = tid; i < n_tab; i += nthreads) {
     const int rg = i / row, wb = i - rg * row;
     uint32_t b = 0;

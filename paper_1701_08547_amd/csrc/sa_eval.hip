@@ -131,21 +131,23 @@ struct Evaluator {
     FVec<ITEMS> K;
   };
 
+  // `base` is wave-uniform: each column's chunk address is a scalar base
+  // plus the lane's constant offset.
   __device__ __forceinline__ Cols load_chunk(int64_t base) const {
     Cols c;
-    const int64_t o = base + ITEMS * lane;
+    const int lo = ITEMS * lane;
     if constexpr (MODE != Mode::Keys) {
-      c.T = *(const IVec<ITEMS> *)(L.cfg.block + o);
-      c.U = *(const IVec<ITEMS> *)(L.cfg.unroll + o);
-      c.R = *(const IVec<ITEMS> *)(L.cfg.regs + o);
+      c.T = *(const IVec<ITEMS> *)((L.cfg.block + base) + lo);
+      c.U = *(const IVec<ITEMS> *)((L.cfg.unroll + base) + lo);
+      c.R = *(const IVec<ITEMS> *)((L.cfg.regs + base) + lo);
       if (HAS_GRID) {
-        c.G = *(const IVec<ITEMS> *)(L.cfg.grid + o);
+        c.G = *(const IVec<ITEMS> *)((L.cfg.grid + base) + lo);
       } else {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) c.G.v[i] = 1;
       }
     } else {
-      c.K = *(const FVec<ITEMS> *)(L.keys + o);
+      c.K = *(const FVec<ITEMS> *)((L.keys + base) + lo);
     }
     return c;
   }
@@ -194,7 +196,7 @@ struct Evaluator {
     int64_t body = e;
     if (L.vec) {
       int64_t a0 = (e + ITEMS - 1) & ~(int64_t)(ITEMS - 1);
-      a0 = a0 < pe ? a0 : pe;
+      a0 = uniform64(a0 < pe ? a0 : pe);  // keep the chunk bases in scalar registers
       if (a0 > e) masked(e, a0);
       body = a0;
       const int64_t nfull = (pe - a0) / kC;
@@ -249,8 +251,8 @@ void sa_eval_kernel(EvalLaunch L) {
   // per register-granule count.
   extern __shared__ __align__(16) uint8_t dyn_lds[];
   __shared__ float tab_rcap[kMaxWB + 1];
-  __shared__ uint32_t tab_mwb[kMaxWB + 1];
-  __shared__ uint8_t tab_blim[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 2];
+  __shared__ uint8_t tab_blim[kMaxWB + 2];
   __shared__ WaveLds wl[kWavesPerBlock];
 
   const KArch &A = L.arch;
@@ -367,8 +369,8 @@ template <Mode MODE, bool HAS_GRID, bool TOPK, int ITEMS, int WPB>
 __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev P) {
   extern __shared__ __align__(16) uint8_t dyn_lds[];
   __shared__ float tab_rcap[kMaxWB + 1];
-  __shared__ uint32_t tab_mwb[kMaxWB + 1];
-  __shared__ uint8_t tab_blim[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 2];
+  __shared__ uint8_t tab_blim[kMaxWB + 2];
   __shared__ WaveLds wl[WPB];
   __shared__ uint64_t wgk[WPB][SA_K_MAX];
 
@@ -569,8 +571,8 @@ namespace {
 __global__ __launch_bounds__(kBlockThreads) void sa_suggest_kernel(EvalLaunch L, uint64_t *kept) {
   extern __shared__ __align__(16) uint8_t dyn_lds[];
   __shared__ float tab_rcap[kMaxWB + 1];
-  __shared__ uint32_t tab_mwb[kMaxWB + 1];
-  __shared__ uint8_t tab_blim[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 2];
+  __shared__ uint8_t tab_blim[kMaxWB + 2];
   build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, threadIdx.x, kBlockThreads);
   const uint64_t full = full_occupancy_mask(L.arch, dyn_lds);
   for (int64_t v = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; v < L.n_var;
