@@ -40,7 +40,7 @@ EXPORTED = (
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure",
-    "sa_suggest", "sa_score_suggested",
+    "sa_suggest", "sa_score_suggested", "sa_gen_configs",
 )
 MLP_PARAMS = 20865
 MLP_FLAT = 20992
@@ -135,6 +135,8 @@ def lib():
             L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64, vp, vp, sz,
                                                   vp]
             L.sa_surrogate_train_step.restype = i32
+            L.sa_gen_configs.argtypes = [ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp]
+            L.sa_gen_configs.restype = i32
             L.sa_suggest.argtypes = [P(SaArch), P(SaVariants), i64, vp, vp]
             L.sa_suggest.restype = i32
             L.sa_score_suggested.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp,

@@ -161,3 +161,79 @@ def custom_batch(seed: int, sizes, with_grid: bool = True, n_cu: int = 256, valu
     T, U, R = col("block"), col("unroll"), col("regs")
     G = col("grid") if with_grid else None
     return Batch(variant_features(n_var, 1000 + int(seed)), seg, T, U, R, G, name)
+
+
+# ---------------------------------------------------------------- streamed batches
+
+# SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) read at an arbitrary
+# position: the same counter-based definition the device generator
+# (sa_gen_configs) implements, so any row of a streamed batch can be rebuilt
+# here for spot checks.
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64_at(seed: int, k) -> np.ndarray:
+    """Output number k (array) of the SplitMix64 sequence seeded with `seed`."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (k + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _pick(u: np.ndarray, n: int) -> np.ndarray:
+    return (((u >> np.uint64(32)) * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+
+
+def streamed_rows(seed: int, e_idx, n_cu: int = 256, with_grid: bool = True):
+    """(T, U, R, G) of global evaluations `e_idx`, as the device generates them."""
+    e = np.asarray(e_idx, dtype=np.uint64) * np.uint64(4)
+    T = (64 * (_pick(splitmix64_at(seed, e), 16) + 1)).astype(np.int32)
+    U = (_pick(splitmix64_at(seed, e + np.uint64(1)), 8) + 1).astype(np.int32)
+    R = (16 * (_pick(splitmix64_at(seed, e + np.uint64(2)), 32) + 1)).astype(np.int32)
+    G = (n_cu << _pick(splitmix64_at(seed, e + np.uint64(3)), 4)).astype(np.int32) if with_grid else None
+    return T, U, R, G
+
+
+@dataclass
+class StreamedBatch:
+    """A batch whose rows are generated on the device chunk by chunk."""
+
+    variants: dict
+    seg: np.ndarray     # int64[n_var + 1]
+    seed: int
+    n_cu: int
+    name: str = ""
+
+    @property
+    def n_var(self) -> int:
+        return int(self.seg.shape[0] - 1)
+
+    @property
+    def n_evals(self) -> int:
+        return int(self.seg[-1])
+
+    def subset(self, vids) -> Batch:
+        """Variants `vids` with their rows rebuilt on the host (local CSR)."""
+        vids = np.asarray(vids, dtype=np.int64)
+        sizes = self.seg[vids + 1] - self.seg[vids]
+        seg = np.zeros(vids.size + 1, dtype=np.int64)
+        np.cumsum(sizes, out=seg[1:])
+        idx = np.concatenate([np.arange(self.seg[v], self.seg[v + 1], dtype=np.int64) for v in vids]) \
+            if vids.size else np.zeros(0, np.int64)
+        T, U, R, G = streamed_rows(self.seed, idx, self.n_cu)
+        var = {k: np.ascontiguousarray(a[vids]) for k, a in self.variants.items()}
+        return Batch(var, seg, T, U, R, G, self.name + "-subset")
+
+
+def c4(n_cu: int = 256, n_var: int = 100000) -> StreamedBatch:
+    """100,000 variants with search spaces log-uniform in [256, 1,048,576]
+    (about 1.26e10 evaluations), rows generated on the device."""
+    sizes = loguniform_sizes(n_var, 256, 1 << 20, 4)
+    seg = np.zeros(n_var + 1, dtype=np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    seed = int(np.random.SeedSequence([SEED_ROOT, 4, 2]).generate_state(1, np.uint64)[0])
+    return StreamedBatch(variant_features(n_var, 4), seg, seed, n_cu, "c4")

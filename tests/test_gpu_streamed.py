@@ -1,0 +1,98 @@
+"""GPU tests of streamed batches: the device row generator against its CPU
+replica (bit-exact), and chunked plain and corrected scoring against the
+oracle and the unchunked corrected pass on sampled variants."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1701_08547_amd import api, streamed, workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def say(*a):
+    print("[gpu-streamed]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def small_batch(n_var=300, seed_id=40):
+    sizes = workloads.loguniform_sizes(n_var, 256, 1 << 20, seed_id)
+    seg = np.zeros(n_var + 1, np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    seed = int(np.random.SeedSequence([workloads.SEED_ROOT, seed_id, 2]).generate_state(1, np.uint64)[0])
+    return workloads.StreamedBatch(workloads.variant_features(n_var, seed_id), seg, seed, 256, "streamed-small")
+
+
+def test_generator_matches_replica():
+    seed = 0x1234ABCD5678EF01
+    for e0, n in [(0, 1000), (12345, 100000), (12_000_000_000, 4097)]:
+        cols = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(4)]
+        p = lambda t: __import__("ctypes").c_void_p(t.data_ptr())
+        assert api.lib().sa_gen_configs(seed, e0, n, 256, p(cols[0]), p(cols[1]), p(cols[2]), p(cols[3]), None) == 0
+        torch.cuda.synchronize()
+        ref = workloads.streamed_rows(seed, np.arange(e0, e0 + n, dtype=np.int64), 256)
+        for c, r in zip(cols, ref):
+            assert np.array_equal(c.cpu().numpy(), r)
+    assert api.lib().sa_gen_configs(seed, -1, 10, 256, None, None, None, None, None) == -1
+
+
+def test_chunk_bounds():
+    seg = np.array([0, 5, 10, 100, 101, 150], np.int64)
+    b = streamed.chunk_bounds(seg, 20)
+    assert b == [(0, 2), (2, 3), (3, 5)]
+    covered = [v for v0, v1 in b for v in range(v0, v1)]
+    assert covered == list(range(5))
+
+
+def test_streamed_plain_and_corrected():
+    arch = oracle.arch_cdna4()
+    b = small_batch()
+    say("n_var", b.n_var, "n_evals", b.n_evals)
+    p = mlp.init_params(seed=4)
+    sur = api.Surrogate(p, np.zeros(24, np.float32) + 0.5, np.ones(24, np.float32) * 0.7)
+    st = streamed.Streamed(b, arch, k=16, chunk_evals=1 << 22, surrogate=sur)
+    assert len(st.chunks) > 3
+    st.run()
+    torch.cuda.synchronize()
+    idx, val = st.idx.cpu().numpy(), st.val.cpu().numpy()
+    idx_c, val_c = st.idx_c.cpu().numpy(), st.val_c.cpu().numpy()
+    g = np.random.default_rng(0)
+    sizes = b.seg[1:] - b.seg[:-1]
+    pick = np.unique(np.concatenate([g.choice(b.n_var, 10, replace=False), [int(np.argmax(sizes))]]))
+    sub = b.subset(pick)
+    ref = oracle.run(arch, sub.variants, sub.configs(), k=16)
+    assert np.array_equal(idx[pick], ref["idx"])
+    assert np.array_equal(val[pick].view(np.uint32), ref["val"].view(np.uint32))
+    var, cfg = api.device_batch(sub)
+    got = api.score(arch, var, cfg, k=16, mlp=sur, want_score=False, want_occ=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(idx_c[pick], got["idx"].cpu().numpy())
+    assert np.array_equal(val_c[pick].view(np.uint32), got["val"].cpu().numpy().view(np.uint32))
+    # every variant got a full row of legal selections
+    assert np.all(idx[:, 0] >= 0) and np.all(idx_c[:, 0] >= 0)
+
+
+def test_streamed_graph_replay_matches_eager():
+    arch = oracle.arch_cdna4()
+    b = small_batch(120, 41)
+    st = streamed.Streamed(b, arch, k=8, chunk_evals=1 << 22, surrogate=None)
+    st.run(corrected=False)
+    torch.cuda.synchronize()
+    eager = st.idx.clone(), st.val.clone()
+    st.idx.fill_(-7)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        st.run(corrected=False)
+    for _ in range(3):
+        st.idx.fill_(-7)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(st.idx, eager[0]) and torch.equal(st.val.view(torch.int32), eager[1].view(torch.int32))
