@@ -43,14 +43,6 @@ def test_generator_matches_replica():
     assert api.lib().sa_gen_configs(seed, -1, 10, 256, None, None, None, None, None) == -1
 
 
-def test_chunk_bounds():
-    seg = np.array([0, 5, 10, 100, 101, 150], np.int64)
-    b = streamed.chunk_bounds(seg, 20)
-    assert b == [(0, 2), (2, 3), (3, 5)]
-    covered = [v for v0, v1 in b for v in range(v0, v1)]
-    assert covered == list(range(5))
-
-
 def test_streamed_plain_and_corrected():
     arch = oracle.arch_cdna4()
     b = small_batch()
