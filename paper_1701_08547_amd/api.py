@@ -498,15 +498,21 @@ class Plan:
 
 
 def autotune(arch: dict, variants: dict, configs: dict, k: int = 8, reps: int = 3, outputs: dict | None = None,
-             stream=None):
-    """Fastest plan shape for this batch (sa_plan_autotune): (shape, ms)."""
+             stream=None, want_score: bool = True, want_occ: bool = True):
+    """Fastest plan shape for this batch (sa_plan_autotune): (shape, ms).
+    Timed with the outputs a later scoring pass writes (per-evaluation score
+    and occupancy only when asked for)."""
     torch = _torch()
     sh = _seg_host(configs["seg"])
     n_var, n_evals = sh.shape[0] - 1, int(sh[-1])
     dev = configs["seg"].device
     o = dict(outputs or {})
-    o.setdefault("occ", torch.empty(n_evals, dtype=torch.int32, device=dev))
-    o.setdefault("score", torch.empty(n_evals, dtype=torch.float32, device=dev))
+    if want_occ:
+        o.setdefault("occ", torch.empty(n_evals, dtype=torch.int32, device=dev))
+    if want_score:
+        o.setdefault("score", torch.empty(n_evals, dtype=torch.float32, device=dev))
+    o.setdefault("occ", None)
+    o.setdefault("score", None)
     o.setdefault("idx", torch.empty((n_var, k), dtype=torch.int32, device=dev))
     o.setdefault("val", torch.empty((n_var, k), dtype=torch.float32, device=dev))
     ws = Workspace(int(lib().sa_plan_autotune_workspace_bytes(n_var, n_evals, k)), dev)

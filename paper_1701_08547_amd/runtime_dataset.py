@@ -16,6 +16,9 @@ inputs N(0, 1).
 
 CLI (GPU): python -m paper_1701_08547_amd.runtime_dataset --per-family 500 \\
               --out runtime.npz
+A large dataset is measured in parts (--family, --part/--parts, --times-only:
+only the timings and the instance list are written) and assembled on any
+host with --assemble, which recomputes the static rows.
 """
 from __future__ import annotations
 
@@ -165,6 +168,50 @@ def build(per_family: int, seed: int = 0, device="cuda", log=None) -> dict:
     return rows
 
 
+def select(instances, family=None, part: int = 0, parts: int = 1):
+    """Indices of one contiguous share of the instances (optionally of one
+    family): part `part` of `parts` equal slices."""
+    idx = [i for i, (f, _) in enumerate(instances) if family is None or f == family]
+    lo, hi = len(idx) * part // parts, len(idx) * (part + 1) // parts
+    return idx[lo:hi]
+
+
+def measure_part(per_family: int, seed: int = 0, family=None, part: int = 0, parts: int = 1, device="cuda",
+                 log=None) -> dict:
+    """Timings of one share of the sampled instances, with their indices."""
+    import torch
+
+    n_cu = torch.cuda.get_device_properties(device).multi_processor_count
+    inst = sample_instances(per_family, seed)
+    idx = select(inst, family, part, parts)
+    ms = measure([inst[i] for i in idx], n_cu, device, seed=seed, log=log)
+    return {"index": np.asarray(idx, np.int64), "ms": ms, "n_cu": np.array([n_cu]),
+            "per_family": np.array([per_family]), "seed": np.array([seed])}
+
+
+def assemble(parts) -> dict:
+    """Rows of the instances covered by the given parts (dicts or paths of
+    `measure_part` outputs taken from one sampling): timings in instance
+    order, static model inputs recomputed here."""
+    parts = [load(p) if isinstance(p, str) else p for p in parts]
+    meta = {(int(p["per_family"][0]), int(p["seed"][0]), int(p["n_cu"][0])) for p in parts}
+    if len(meta) != 1:
+        raise ValueError("parts come from different samplings or devices: %s" % sorted(meta))
+    per_family, seed, n_cu = meta.pop()
+    idx = np.concatenate([p["index"] for p in parts])
+    ms = np.concatenate([p["ms"] for p in parts])
+    if np.unique(idx).size != idx.size:
+        raise ValueError("parts overlap")
+    order = np.argsort(idx, kind="stable")
+    idx, ms = idx[order], ms[order]
+    inst = sample_instances(per_family, seed)
+    rows = static_rows([inst[i] for i in idx], n_cu)
+    rows["ms"] = ms.reshape(-1)
+    rows["instance"] = np.repeat(np.arange(idx.size, dtype=np.int32), N_CFG)
+    rows["n_cu"] = np.array([n_cu])
+    return rows
+
+
 def save(path: str, data: dict):
     np.savez_compressed(path, **data)
 
@@ -178,11 +225,21 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--per-family", type=int, default=500)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--family", choices=FAMILIES)
+    ap.add_argument("--part", type=int, default=0)
+    ap.add_argument("--parts", type=int, default=1)
+    ap.add_argument("--times-only", action="store_true")
+    ap.add_argument("--assemble", nargs="+", metavar="PART")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     t0 = time.time()
-    d = build(a.per_family, a.seed, log=log)
+    if a.times_only:
+        d = measure_part(a.per_family, a.seed, a.family, a.part, a.parts, log=log)
+        save(a.out, d)
+        print(json.dumps({"instances": int(d["index"].size), "seconds": time.time() - t0}), flush=True)
+        return 0
+    d = assemble(a.assemble) if a.assemble else build(a.per_family, a.seed, log=log)
     save(a.out, d)
     print(json.dumps({"rows": int(d["ms"].size), "instances": int(d["instance"].max() + 1),
                       "seconds": time.time() - t0}), flush=True)

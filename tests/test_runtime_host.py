@@ -127,3 +127,25 @@ def test_instance_sampling():
             assert lo <= n <= hi
     T, U = rd.config_grid()
     assert T.size == 128 and len(set(zip(T.tolist(), U.tolist()))) == 128
+
+
+def test_parts_cover_and_assemble():
+    inst = rd.sample_instances(3, 5)
+    shares = [rd.select(inst, f, p, 2) for f in rd.FAMILIES for p in range(2)]
+    assert sorted(i for s in shares for i in s) == list(range(len(inst)))
+    mk = lambda idx: {"index": np.asarray(idx, np.int64),
+                      "ms": np.arange(len(idx) * rd.N_CFG, dtype=np.float32).reshape(len(idx), rd.N_CFG) + 1000 * idx[0],
+                      "n_cu": np.array([256]), "per_family": np.array([3]), "seed": np.array([5])}
+    parts = [mk(s) for s in shares if s]
+    rows = rd.assemble(parts[::-1])                  # any order of parts
+    assert rows["ms"].size == len(inst) * rd.N_CFG
+    assert rows["n"].tolist()[::rd.N_CFG] == [n for _, n in inst]
+    assert rows["ms"][:rd.N_CFG].tolist() == parts[0]["ms"][0].tolist()
+    direct = rd.static_rows(inst, 256)
+    for f in rd.COUNT_FIELDS + ("block", "unroll", "grid", "regs"):
+        assert np.array_equal(rows[f], direct[f])
+    with pytest.raises(ValueError):
+        rd.assemble([parts[0], parts[0]])
+    other = dict(parts[1], seed=np.array([6]))
+    with pytest.raises(ValueError):
+        rd.assemble([parts[0], other])
