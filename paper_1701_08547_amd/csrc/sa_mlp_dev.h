@@ -41,8 +41,6 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   const bf16x2_t p = {(__bf16)lo, (__bf16)hi};
   return __builtin_bit_cast(uint32_t, p);
 }
-__device__ __forceinline__ float bf_lo(uint32_t p) { return __uint_as_float(p << 16); }
-__device__ __forceinline__ float bf_hi(uint32_t p) { return __uint_as_float(p & 0xFFFF0000u); }
 
 // erf for x = |a| / sqrt 2 by Abramowitz & Stegun 7.1.26 (absolute error at
 // most 1.5e-7): 1 - erf(x) = t P(t) exp(-x^2), t = 1 / (1 + p x).  Returns
@@ -84,13 +82,25 @@ typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float phi_exact(float x) { return 0.5f * erfcf(-x * 0.70710678118654752f); }
 
-__device__ __forceinline__ float gelu_tab(float a, const f32x2_t *tab) {
-  float t = fmaf(a, 32.0f, 256.0f);
-  t = __builtin_amdgcn_fmed3f(t, 0.0f, 511.99997f);
-  const int i = (int)t;
-  const float f = t - (float)i;
-  const f32x2_t e = tab[i];
-  return a * fmaf(f, e.y, e.x);
+// GELU of N values in place.  All table positions are computed first and all
+// reads issued before the first interpolation, so that the reads' latency
+// overlaps instead of being paid once per value.  For t in [0, 512) the
+// fractional part t - floor(t) is exact.
+template <int N>
+__device__ __forceinline__ void gelu_tab_n(float (&a)[N], const f32x2_t *tab) {
+  int idx[N];
+  float fr[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float t = __builtin_amdgcn_fmed3f(fmaf(a[i], 32.0f, 256.0f), 0.0f, 511.99997f);
+    idx[i] = (int)t;
+    fr[i] = __builtin_amdgcn_fractf(t);
+  }
+  f32x2_t e[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) e[i] = tab[idx[i]];
+#pragma unroll
+  for (int i = 0; i < N; ++i) a[i] = a[i] * fmaf(fr[i], e[i].y, e[i].x);
 }
 
 // ---------------------------------------------------------------- features
@@ -138,7 +148,8 @@ __device__ __forceinline__ void config_features(float *f, int32_t T, int32_t U, 
 struct __align__(16) MlpLdsT {
   uint16_t W1[kMH * kLdW1];  // W1[h][k]
   uint16_t W2[kMH * kLdW2];  // W2[o][.], columns permuted per 32-wide chunk (see w2_column)
-  float b1[kMH], b2[kMH], w3[kMH];
+  uint16_t w3p[kMH];         // w3 in the same permuted order
+  float b1[kMH], b2[kMH];
   f32x2_t phi[kGeluN + 1];   // (Phi(a_i), Phi(a_i+1) - Phi(a_i))
   float mean[kMF], inv_std[kMF];
   float b3;
@@ -161,7 +172,7 @@ __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthread
   for (int i = tid; i < kMH; i += nthreads) {
     s.b1[i] = M.b1[i];
     s.b2[i] = M.b2[i];
-    s.w3[i] = __uint_as_float((uint32_t)M.w3[i] << 16);
+    s.w3p[i] = M.w3[w2_column(i)];
   }
   for (int i = tid; i < kMF; i += nthreads) {
     s.mean[i] = M.mean[i];
@@ -200,8 +211,12 @@ __device__ __forceinline__ f32x4_t mfma32(u32x4_t a, u32x4_t b, f32x4_t c) {
 
 // Delta of row `lane` of the wave's 64-row input block X (put_x rows; the
 // caller orders the writes before this call).  h1 = bf16(GELU(W1 x + b1)),
-// h2 = bf16(GELU(W2 h1 + b2)), Delta = w3 . h2 + b3: fp32 accumulation,
-// the final sum over the four lane groups combined pairwise.
+// h2 = bf16(GELU(W2 h1 + b2)), Delta = w3 . h2 + b3, all three layers on the
+// matrix cores with fp32 accumulation.  A layer's output tiles (hidden units
+// 16 t + 4 q + j of row r at lane 16 q + r) are, packed in pairs, the B
+// operands of the next layer once its weight columns are permuted as in
+// w2_column.  The third layer multiplies every A row by w3, so row 4 q of its
+// result, which lane 16 q + r holds, is the sum for row r of the row tile.
 __device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, int lane) {
   const int r = lane & 15, q = lane >> 4;
   u32x4_t xb[4];
@@ -213,51 +228,65 @@ __device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, i
   for (int t = 0; t < 8; ++t) {
     const u32x4_t a = *(const u32x4_t *)(s.W1 + (16 * t + r) * kLdW1 + 8 * q);
     const f32x4_t bias = *(const f32x4_t *)(s.b1 + 16 * t + 4 * q);
+    float v[16];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
       const f32x4_t d = mfma32(a, xb[rt], bias);
-      h1[t][rt][0] = pack_bf16(gelu_tab(d[0], s.phi), gelu_tab(d[1], s.phi));
-      h1[t][rt][1] = pack_bf16(gelu_tab(d[2], s.phi), gelu_tab(d[3], s.phi));
-    }
-  }
-  // layer 2, layer 3 folded into its epilogue
-  float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
-  for (int ot = 0; ot < 8; ++ot) {
-    const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
-    f32x4_t acc[4] = {bias, bias, bias, bias};
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        const u32x4_t b = {h1[2 * c][rt][0], h1[2 * c][rt][1], h1[2 * c + 1][rt][0], h1[2 * c + 1][rt][1]};
-        acc[rt] = mfma32(a, b, acc[rt]);
-      }
+      for (int j = 0; j < 4; ++j) v[4 * rt + j] = d[j];
     }
-    const f32x4_t w = *(const f32x4_t *)(s.w3 + 16 * ot + 4 * q);
+    gelu_tab_n<16>(v, s.phi);
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
-      const uint32_t p0 = pack_bf16(gelu_tab(acc[rt][0], s.phi), gelu_tab(acc[rt][1], s.phi));
-      const uint32_t p1 = pack_bf16(gelu_tab(acc[rt][2], s.phi), gelu_tab(acc[rt][3], s.phi));
-      float v = part[rt];
-      v = fmaf(bf_lo(p0), w[0], v);
-      v = fmaf(bf_hi(p0), w[1], v);
-      v = fmaf(bf_lo(p1), w[2], v);
-      v = fmaf(bf_hi(p1), w[3], v);
-      part[rt] = v;
+      h1[t][rt][0] = pack_bf16(v[4 * rt], v[4 * rt + 1]);
+      h1[t][rt][1] = pack_bf16(v[4 * rt + 2], v[4 * rt + 3]);
     }
   }
+  // layers 2 and 3, one 32-unit chunk of the second hidden layer at a time
+  f32x4_t acc3[4];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    part[rt] += __shfl_xor(part[rt], 16);
-    part[rt] += __shfl_xor(part[rt], 32);
+  for (int rt = 0; rt < 4; ++rt) acc3[rt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+  for (int c3 = 0; c3 < 4; ++c3) {
+    uint32_t h2[2][4][2];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int ot = 2 * c3 + half;
+      const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
+      f32x4_t acc[4] = {bias, bias, bias, bias};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const u32x4_t b = {h1[2 * c][rt][0], h1[2 * c][rt][1], h1[2 * c + 1][rt][0], h1[2 * c + 1][rt][1]};
+          acc[rt] = mfma32(a, b, acc[rt]);
+        }
+      }
+      float v[16];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * rt + j] = acc[rt][j];
+      gelu_tab_n<16>(v, s.phi);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        h2[half][rt][0] = pack_bf16(v[4 * rt], v[4 * rt + 1]);
+        h2[half][rt][1] = pack_bf16(v[4 * rt + 2], v[4 * rt + 3]);
+      }
+    }
+    const u32x4_t a3 = *(const u32x4_t *)(s.w3p + 32 * c3 + 8 * q);
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const u32x4_t b = {h2[0][rt][0], h2[0][rt][1], h2[1][rt][0], h2[1][rt][1]};
+      acc3[rt] = mfma32(a3, b, acc3[rt]);
+    }
   }
   // lane l = 16 q + r owns row l, which is row r of row tile q
-  float d = part[0];
-  d = q == 1 ? part[1] : d;
-  d = q == 2 ? part[2] : d;
-  d = q == 3 ? part[3] : d;
+  float d = acc3[0][0];
+  d = q == 1 ? acc3[1][0] : d;
+  d = q == 2 ? acc3[2][0] : d;
+  d = q == 3 ? acc3[3][0] : d;
   return d + s.b3;
 }
 

@@ -199,7 +199,10 @@ int32_t sa_rt_measure(int32_t family, int64_t n, const float *a, const float *b,
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t ev[2 * 64];
   for (int i = 0; i < 2 * reps; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) return rt_fail(-5, "hipEventCreate failed");
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      return rt_fail(-5, "hipEventCreate failed");
+    }
   int32_t status = 0;
   std::vector<float> t(reps);
   for (int32_t ci = 0; ci < n_cfg && status == 0; ++ci) {
@@ -211,20 +214,24 @@ int32_t sa_rt_measure(int32_t family, int64_t n, const float *a, const float *b,
     for (int w = 0; w < warmup && status == 0; ++w)
       if (launch(family, n, T[ci], U[ci], G, a, b, c, s) != hipSuccess) status = rt_fail(-5, "launch failed");
     for (int r = 0; r < reps && status == 0; ++r) {
-      hipEventRecord(ev[2 * r], s);
-      if (launch(family, n, T[ci], U[ci], G, a, b, c, s) != hipSuccess) status = rt_fail(-5, "launch failed");
-      hipEventRecord(ev[2 * r + 1], s);
+      if (hipEventRecord(ev[2 * r], s) != hipSuccess ||
+          launch(family, n, T[ci], U[ci], G, a, b, c, s) != hipSuccess ||
+          hipEventRecord(ev[2 * r + 1], s) != hipSuccess)
+        status = rt_fail(-5, "launch or event record failed");
     }
     if (status) break;
     if (hipEventSynchronize(ev[2 * reps - 1]) != hipSuccess) {
       status = rt_fail(-5, "hipEventSynchronize failed");
       break;
     }
-    for (int r = 0; r < reps; ++r) hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+    for (int r = 0; r < reps && status == 0; ++r)
+      if (hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]) != hipSuccess)
+        status = rt_fail(-5, "hipEventElapsedTime failed");
+    if (status) break;
     std::sort(t.begin(), t.end());
     ms_out[ci] = t[keep - 1];
   }
-  for (int i = 0; i < 2 * reps; ++i) hipEventDestroy(ev[i]);
+  for (int i = 0; i < 2 * reps; ++i) (void)hipEventDestroy(ev[i]);
   return status;
 }
 
