@@ -269,6 +269,22 @@ sa_status sa_topk(const float *keys, const int64_t *seg, int64_t n_variants, int
 sa_status sa_suggest(const sa_arch *arch, const sa_variants *variants, int64_t n_variants, uint64_t *kept,
                      void *stream);
 
+/*
+ * Headroom at full occupancy (Sec. III-C; the R* and S* columns of Table VII):
+ * for the block size T = block[i] of each row, the largest register count per
+ * thread and the largest LDS per workgroup at which occupancy (Eqs. 1-5) is
+ * still full, the other resource not limiting.  r_star[i] = max(0, largest
+ * such register count - regs[i]) (regs NULL: 0 registers in use);
+ * s_star[i] = the largest such LDS size in bytes (at most the per-workgroup
+ * limit).  Both are 0 when T cannot reach full occupancy, when T lies outside
+ * [1, max_threads_per_block], or when regs[i] lies outside
+ * [0, max_vgprs_per_thread].  block, regs, r_star, s_star: int32[n], 4-byte
+ * aligned device arrays; either output may be NULL, not both.  Asynchronous
+ * on `stream`.
+ */
+sa_status sa_headroom(const sa_arch *arch, const int32_t *block, const int32_t *regs, int64_t n, int32_t *r_star,
+                      int32_t *s_star, void *stream);
+
 /* sa_score's pass with the top-k restricted to the reduced space: only
  * evaluations whose block size is kept by sa_suggest's rule compete; the
  * optional occupancy and score outputs cover every evaluation.  k in

@@ -40,7 +40,7 @@ EXPORTED = (
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure",
-    "sa_suggest", "sa_score_suggested", "sa_gen_configs",
+    "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
 )
 MLP_PARAMS = 20865
 MLP_FLAT = 20992
@@ -142,6 +142,8 @@ def lib():
             L.sa_score_suggested.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp,
                                              vp, sz, vp]
             L.sa_score_suggested.restype = i32
+            L.sa_headroom.argtypes = [P(SaArch), vp, vp, i64, vp, vp, vp]
+            L.sa_headroom.restype = i32
             L.sa_rt_last_error.restype = ctypes.c_char_p
             L.sa_rt_grid.argtypes = [i32, i64, i32, i32, i32]
             L.sa_rt_grid.restype = i64
@@ -338,6 +340,20 @@ def suggest(arch: dict, variants: dict, out=None, stream=None):
     _check(lib().sa_suggest(ctypes.byref(a), ctypes.byref(_variants_struct(variants)), n_var,
                             _ptr(out, torch.int64, "kept"), _stream(stream)))
     return out
+
+
+def headroom(arch: dict, block, regs=None, stream=None):
+    """Registers per thread still free (R*) and LDS per workgroup (S*) at
+    full occupancy for each row's block size (sa_headroom): two int32
+    tensors."""
+    torch = _torch()
+    n = int(block.shape[0])
+    r_star = torch.empty(n, dtype=torch.int32, device=block.device)
+    s_star = torch.empty(n, dtype=torch.int32, device=block.device)
+    a = _arch_struct(arch)
+    _check(lib().sa_headroom(ctypes.byref(a), _ptr(block, torch.int32, "block"), _ptr(regs, torch.int32, "regs"), n,
+                             _ptr(r_star, torch.int32), _ptr(s_star, torch.int32), _stream(stream)))
+    return r_star, s_star
 
 
 def score_suggested(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: bool = False,

@@ -31,7 +31,7 @@ import time
 
 import numpy as np
 
-from . import api
+from . import api, runtime_dataset
 from .runtime_dataset import COUNT_FIELDS, FAMILIES, N_CFG, load
 
 
@@ -94,6 +94,18 @@ def spearman(a: np.ndarray, b: np.ndarray) -> float:
 
 def regret(key: np.ndarray, t: np.ndarray) -> float:
     return float(t[int(np.argmin(key))] / t.min() - 1.0)
+
+
+SEARCH_K = (1, 2, 4, 8, 16)
+
+
+def search_regret(key: np.ndarray, t: np.ndarray, k: int):
+    """Model-guided empirical search (the use Sec. III-C makes of the model:
+    it narrows the space the autotuner then times): time the k configurations
+    the key ranks first (ties to the lower index) and keep the fastest.
+    Returns its regret and the share of a full sweep's timing spent."""
+    order = np.argsort(key, kind="stable")[:k]
+    return float(t[order].min() / t.min() - 1.0), float(t[order].sum() / t.sum())
 
 
 def bootstrap_ci(x: np.ndarray, reps: int = 2000, seed: int = 0):
@@ -173,6 +185,14 @@ def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, 
                "regret_corrected": float(rc.mean()), "regret_corrected_ci": bootstrap_ci(rc),
                "regret_diff_ci": bootstrap_ci(rp - rc),
                "spearman_plain": float(sp.mean()), "spearman_corrected": float(sc.mean())}
+        search = {}
+        for k in SEARCH_K:
+            p = np.array([search_regret(ln_s[i], ms[i], k) for i in ids])
+            c = np.array([search_regret(z[i], ms[i], k) for i in ids])
+            search[str(k)] = {"regret_plain": float(p[:, 0].mean()), "regret_corrected": float(c[:, 0].mean()),
+                              "time_share_plain": float(p[:, 1].mean()),
+                              "time_share_corrected": float(c[:, 1].mean())}
+        out["search"] = search
         if pruned is not None:
             out["pruned_fraction"] = float(1.0 - pruned[ids].mean())
             out["regret_pruned_best"] = float(np.nanmean([within(ms[i], ms[i], pruned[i]) for i in ids]))
@@ -230,7 +250,9 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--data", required=True)
+    src = ap.add_mutually_exclusive_group(required=True)
+    src.add_argument("--data", help="npz of dataset rows")
+    src.add_argument("--parts", nargs="+", help="timing parts of one sampling, assembled here")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -239,7 +261,8 @@ def main(argv=None):
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
-    sur, rep = run(load(a.data), a.epochs, a.batch, a.lr, a.seed, log=log)
+    data = load(a.data) if a.data else runtime_dataset.assemble(a.parts)
+    sur, rep = run(data, a.epochs, a.batch, a.lr, a.seed, log=log)
     if a.out:
         np.savez(a.out, **{k: np.asarray(v) for k, v in sur.state_dict().items()})
     txt = json.dumps(rep, indent=1)

@@ -372,6 +372,24 @@ sa_status sa_suggest(const sa_arch *arch, const sa_variants *variants, int64_t n
   return e == hipSuccess ? SA_OK : hip_fail(e, "sa_suggest_kernel launch");
 }
 
+sa_status sa_headroom(const sa_arch *arch, const int32_t *block, const int32_t *regs, int64_t n, int32_t *r_star,
+                      int32_t *s_star, void *stream) {
+  sa_status st;
+  if ((st = check_arch(arch)) != SA_OK) return st;
+  if (n < 0) return fail(SA_ERR_ARG, "negative n");
+  if (n == 0) return SA_OK;
+  if (!block) return fail(SA_ERR_ARG, "block is NULL");
+  if (!r_star && !s_star) return fail(SA_ERR_ARG, "no output");
+  const void *ps[] = {block, regs, r_star, s_star};
+  for (const void *p : ps)
+    if (p && !aligned(p, 4)) return fail(SA_ERR_ALIGN, "array not 4-byte aligned");
+  sa::EvalLaunch L{};
+  L.arch = to_karch(arch);
+  set_lds_layout(L);
+  hipError_t e = sa::launch_headroom(L, block, regs, n, r_star, s_star, (hipStream_t)stream);
+  return e == hipSuccess ? SA_OK : hip_fail(e, "sa_headroom_kernel launch");
+}
+
 sa_status sa_score_suggested(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
                              int64_t n_variants, int64_t n_evals, float *score, int32_t *occ_waves, int32_t k,
                              int32_t *topk_idx, float *topk_val, void *workspace, size_t workspace_bytes,

@@ -579,7 +579,54 @@ __global__ __launch_bounds__(kBlockThreads) void sa_suggest_kernel(EvalLaunch L,
        v += (int64_t)gridDim.x * kBlockThreads)
     kept[v] = kept_mask(full, L.arch.nw, L.var.n_fp[v], L.var.n_ld[v], L.var.n_st[v]);
 }
+
+// Headroom at full occupancy for each row's block size (Sec. III-C): the last
+// register-granule row of the occupancy table that keeps full occupancy at
+// this W_B (rows never gain occupancy as registers grow), and the largest LDS
+// allocation that leaves room for the table's block count, floor(floor(pool /
+// B) / granule) granules (Eq. 5 with a floor).
+__global__ __launch_bounds__(kBlockThreads) void sa_headroom_kernel(EvalLaunch L, const int32_t *block,
+                                                                    const int32_t *regs, int64_t n, int32_t *r_star,
+                                                                    int32_t *s_star) {
+  extern __shared__ __align__(16) uint8_t dyn_lds[];
+  __shared__ float tab_rcap[kMaxWB + 1];
+  __shared__ uint32_t tab_mwb[kMaxWB + 2];
+  __shared__ uint8_t tab_blim[kMaxWB + 2];
+  build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, threadIdx.x, kBlockThreads);
+  const KArch &A = L.arch;
+  const uint8_t *tab_b = dyn_lds;
+  const int32_t row = A.nw + 2;
+  for (int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlockThreads) {
+    const int32_t T = block[i];
+    const int32_t R = regs ? regs[i] : 0;
+    int32_t rs = 0, ss = 0;
+    if ((uint32_t)(T - 1) < (uint32_t)A.max_threads && (uint32_t)R <= (uint32_t)A.max_vgprs) {
+      const int32_t WB = (T + A.ws - 1) >> A.ws_shift;
+      const int32_t B0 = tab_b[WB];
+      if (B0 * WB == A.max_waves) {
+        int32_t g = 0;
+        for (int32_t rg = 1; rg <= A.nr && (int32_t)tab_b[rg * row + WB] * WB == A.max_waves; ++rg) g = rg;
+        const int32_t rmax = g << A.gran_shift;
+        rs = rmax > R ? rmax - R : 0;
+        const int32_t alloc = (A.lds_cu / B0) / A.lds_gran * A.lds_gran;
+        ss = alloc < A.max_lds ? alloc : A.max_lds;
+      }
+    }
+    if (r_star) r_star[i] = rs;
+    if (s_star) s_star[i] = ss;
+  }
+}
 }  // namespace
+
+hipError_t launch_headroom(const EvalLaunch &L, const int32_t *block, const int32_t *regs, int64_t n, int32_t *r_star,
+                           int32_t *s_star, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + kBlockThreads - 1) / kBlockThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(sa_headroom_kernel, dim3((uint32_t)blocks), dim3(kBlockThreads), (size_t)L.dyn_lds_bytes,
+                     stream, L, block, regs, n, r_star, s_star);
+  return hipGetLastError();
+}
 
 hipError_t launch_suggest(const EvalLaunch &L, uint64_t *kept, hipStream_t stream) {
   if (L.n_var == 0) return hipSuccess;

@@ -140,6 +140,8 @@ struct AdamArgs {
 
 hipError_t launch_features(const EvalLaunch &L, float *feat, hipStream_t stream);
 hipError_t launch_suggest(const EvalLaunch &L, uint64_t *kept, hipStream_t stream);
+hipError_t launch_headroom(const EvalLaunch &L, const int32_t *block, const int32_t *regs, int64_t n, int32_t *r_star,
+                           int32_t *s_star, hipStream_t stream);
 hipError_t launch_corrected(const EvalLaunch &L, const MlpDev &M, bool has_grid, hipStream_t stream);
 hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream);
 int64_t train_slabs(int64_t n);

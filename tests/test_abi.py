@@ -171,3 +171,19 @@ def test_suggest_argument_errors(L):
     assert L.sa_score_suggested(ctypes.byref(a), ctypes.byref(v), ctypes.byref(c), 1, 1, None, None, 0,
                                 ctypes.c_void_p(16), None, None, 0, None) == -1
 
+
+
+def test_headroom_argument_errors(L):
+    a = api.SaArch()
+    assert L.sa_arch_gfx950(ctypes.byref(a)) == 0
+    p = ctypes.c_void_p
+    assert L.sa_headroom(ctypes.byref(a), None, None, 4, p(16), None, None) == -1      # block NULL
+    assert L.sa_headroom(ctypes.byref(a), p(16), None, 4, None, None, None) == -1      # no output
+    assert L.sa_headroom(ctypes.byref(a), p(16), None, -1, p(16), None, None) == -1    # negative n
+    assert L.sa_headroom(ctypes.byref(a), p(18), None, 4, p(16), None, None) == -2     # misaligned
+    assert L.sa_headroom(ctypes.byref(a), p(16), None, 4, None, p(22), None) == -2
+    assert L.sa_headroom(ctypes.byref(a), None, None, 0, None, None, None) == 0        # empty
+    bad = api.SaArch()
+    ctypes.memmove(ctypes.byref(bad), ctypes.byref(a), ctypes.sizeof(a))
+    bad.wave_size = 48
+    assert L.sa_headroom(ctypes.byref(bad), p(16), None, 4, p(16), None, None) == -6   # descriptor rejected

@@ -41,3 +41,17 @@ def test_init_params_layout():
     p = correction.init_params(0)
     assert p["W1"].shape == (128, 32) and np.all(p["W1"][:, 24:] == 0)
     assert np.abs(p["W2"]).max() <= 1 / np.sqrt(128)
+
+
+def test_search_regret_hand_case():
+    t = np.array([4.0, 1.0, 2.0, 8.0])
+    key = np.array([0.1, 0.3, 0.2, 0.2])           # ranks: 0, then 2 and 3 tied (lower index first), then 1
+    assert correction.search_regret(key, t, 1) == (3.0, 4.0 / 15.0)
+    assert correction.search_regret(key, t, 2) == (1.0, 6.0 / 15.0)
+    assert correction.search_regret(key, t, 3) == (1.0, 14.0 / 15.0)
+    assert correction.search_regret(key, t, 4) == (0.0, 1.0)
+    # k = 1 is the plain top-1 regret
+    g = np.random.default_rng(3)
+    for _ in range(20):
+        k2, t2 = g.random(128), g.random(128) + 0.1
+        assert correction.search_regret(k2, t2, 1)[0] == correction.regret(k2, t2)

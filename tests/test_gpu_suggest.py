@@ -79,3 +79,56 @@ def test_restricted_topk_matches_oracle(with_grid):
         assert idx[vv].tolist() == want, (vv, idx[vv], want)
         wv = [s for s, _ in keys[:8]] + [np.inf] * (8 - min(8, len(keys)))
         assert np.array_equal(val[vv].astype(np.float32).view(np.uint32), np.array(wv, np.float32).view(np.uint32))
+
+
+def _headroom(arch, T, R=None):
+    b = torch.from_numpy(np.asarray(T, np.int32)).cuda()
+    r = None if R is None else torch.from_numpy(np.asarray(R, np.int32)).cuda()
+    rs, ss = api.headroom(arch, b, r)
+    torch.cuda.synchronize()
+    return rs.cpu().numpy(), ss.cpu().numpy()
+
+
+def test_headroom_table7(golden):
+    """R* and S* of Table VII from the GPU: every reproducible [R^u : R*] row
+    at each suggested thread count, and S* (bytes) at the smallest suggested
+    thread count for the rows with occupancy 1."""
+    t7 = golden("paper_tables.json")["table7_suggested"]
+    rows = [r for r in t7["rows"] if not (r["kernel"] == "matvec2d" and r["gpu"] in ("kepler", "maxwell"))]
+    assert len(rows) == 14
+    for r in rows:
+        a = oracle.arch_paper(r["gpu"])
+        ts = t7["t_star"][r["gpu"]]
+        rs, ss = _headroom(a, ts, [r["R_u"]] * len(ts))
+        assert rs.tolist() == [r["R_star"]] * len(ts), (r, rs)
+        if r["occ"] == 1.0:
+            assert int(ss[ts.index(min(ts))]) == r["S_star"], (r, ss)
+
+
+@pytest.mark.parametrize("name", ["cdna4", "fermi", "kepler", "maxwell", "pascal"])
+def test_headroom_matches_oracle(name):
+    """Every block size from -1 to the limit plus a wave, against the
+    oracle's searches over Eqs. 1-5 (registers by scan, LDS by bisection);
+    out-of-range rows give 0."""
+    a = oracle.arch_cdna4() if name == "cdna4" else oracle.arch_paper(name)
+    ws, tmax, rmax = a["wave_size"], a["max_threads_per_block"], a["max_vgprs_per_thread"]
+    g = a["vgpr_granule"]
+    r_set = sorted({0, 1, g - 1 if g > 1 else 0, g, 16, 21, 32, 40, 63, 64, 65, rmax - 1, rmax, rmax + 1, -1})
+    Ts = list(range(-1, tmax + ws + 1))
+    T = np.repeat(np.array(Ts, np.int32), len(r_set))
+    R = np.tile(np.array(r_set, np.int32), len(Ts))
+    rs, ss = _headroom(a, T, R)
+    rs0, ss0 = _headroom(a, Ts)
+    rfull, sfull = {}, {}
+    for t in Ts:
+        ok = 1 <= t <= tmax
+        rfull[t] = paper.max_registers_at_full(a, t) if ok else 0
+        sfull[t] = paper.max_shared_at_full(a, t) if ok else 0
+    for i, (t, r) in enumerate(zip(T.tolist(), R.tolist())):
+        valid = 1 <= t <= tmax and 0 <= r <= rmax
+        want_r = max(0, rfull[t] - r) if valid else 0
+        want_s = sfull[t] if valid else 0
+        assert (int(rs[i]), int(ss[i])) == (want_r, want_s), (name, t, r, rs[i], ss[i], want_r, want_s)
+    assert rs0.tolist() == [rfull[t] for t in Ts]
+    assert ss0.tolist() == [sfull[t] for t in Ts]
+    say(name, "R* at T = 4 waves:", rfull[4 * ws], "S*:", sfull[4 * ws])
