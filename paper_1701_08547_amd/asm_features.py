@@ -35,6 +35,8 @@ from dataclasses import dataclass, field
 import yaml
 
 CATEGORIES = ("n_fp", "n_int", "n_ld", "n_st", "n_br", "n_bar", "n_reg")
+# issue classes of the hardware's per-wave instruction counters
+HW_CLASSES = ("valu", "salu", "smem", "vmem_rd", "vmem_wr", "lds", "branch")
 
 _FLOAT_TYPES = ("_f16", "_bf16", "_f32", "_f64")
 _LABEL = re.compile(r"^(\.LBB\d+_\d+|; %bb\.\d+):?")
@@ -70,6 +72,33 @@ def category(mnemonic: str) -> str | None:
     return None
 
 
+def hw_class(mnemonic: str) -> str | None:
+    """Issue class of one instruction as the per-wave hardware counters see
+    it (vector ALU including moves and MFMA, scalar ALU, scalar memory,
+    vector memory reads / writes, LDS, branches); None for the rest (waits,
+    barriers, no-ops, end of program)."""
+    m = mnemonic.lower()
+    if m.startswith("v_"):
+        return "valu"
+    if m.startswith("ds_"):
+        return "lds"
+    if m.startswith(("global_load", "buffer_load", "flat_load", "scratch_load")):
+        return "vmem_rd"
+    if m.startswith(("global_store", "buffer_store", "flat_store", "scratch_store", "global_atomic", "buffer_atomic",
+                     "flat_atomic")):
+        return "vmem_wr"
+    if m.startswith(("s_load", "s_buffer_load", "s_scratch_load", "s_dcache", "s_memtime", "s_memrealtime")):
+        return "smem"
+    if m.startswith("s_cbranch") or m in ("s_branch", "s_setpc_b64", "s_swappc_b64"):
+        return "branch"
+    if m.startswith(("s_waitcnt", "s_barrier", "s_nop", "s_endpgm", "s_sleep", "s_setprio", "s_sendmsg", "s_trap",
+                     "s_icache", "s_ttrace", "s_sethalt", "s_set_gpr_idx")):
+        return None
+    if m.startswith("s_"):
+        return "salu"
+    return None
+
+
 @dataclass
 class KernelMix:
     name: str
@@ -80,6 +109,8 @@ class KernelMix:
     vgpr: int = 0
     agpr: int = 0
     lds: int = 0
+    hw_outside: dict = field(default_factory=lambda: dict.fromkeys(HW_CLASSES, 0))
+    hw_loops: list = field(default_factory=list)     # per loop: issue-class counts
 
     @property
     def regs(self) -> int:
@@ -93,6 +124,17 @@ class KernelMix:
         out = dict(self.outside)
         for t, c in zip(trips, self.loops):
             for k in CATEGORIES:
+                out[k] += int(t) * c[k]
+        return out
+
+    def hw_counts(self, trips) -> dict:
+        """Per-wave dynamic counts by issue class for the given trip counts
+        (every lane of the wave taking the same path)."""
+        if len(trips) != len(self.hw_loops):
+            raise ValueError("%s has %d loops, %d trip counts given" % (self.name, len(self.hw_loops), len(trips)))
+        out = dict(self.hw_outside)
+        for t, c in zip(trips, self.hw_loops):
+            for k in HW_CLASSES:
                 out[k] += int(t) * c[k]
         return out
 
@@ -140,6 +182,7 @@ def parse(text: str) -> dict:
                 if hid not in loop_ids:
                     loop_ids[hid] = len(cur.loops)
                     cur.loops.append(dict.fromkeys(CATEGORIES, 0))
+                    cur.hw_loops.append(dict.fromkeys(HW_CLASSES, 0))
                     cur.loop_vec.append(0)
                     cur.loop_div.append(0)
                 block_loop, block_in_loop = loop_ids[hid], True
@@ -154,6 +197,12 @@ def parse(text: str) -> dict:
             mask_stack.append(block_in_loop)
         elif mn.startswith("s_or_b64") and "exec, exec" in s and mask_stack:
             mask_stack.pop()
+        hw = hw_class(mn)
+        if hw:
+            if block_loop is None:
+                cur.hw_outside[hw] += 1
+            else:
+                cur.hw_loops[block_loop][hw] += 1
         cat = category(mn)
         if cat is None and not _is_vector(mn):
             continue

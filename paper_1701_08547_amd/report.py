@@ -3,7 +3,8 @@ object per workload:
 
   c0  one variant x 4,096 configurations (block x unroll x registers), top-8:
       launch-bound, so the figure is the time per launch, eager (host call
-      included) and inside a graph of back-to-back launches;
+      included) and inside a graph of back-to-back launches, for the
+      autotuned plan shape;
   c2  10,000 variants with search spaces log-uniform in [64, 262,144]
       (about 3.2e8 evaluations), grid column present, top-16 fused, no
       per-evaluation outputs: the plan shape is autotuned (tiles
@@ -66,11 +67,16 @@ def _bytes(b, k: int) -> int:
 
 
 def c0(arch: dict, steps: int, warmup: int) -> dict:
+    import torch
+
     b = workloads.c0()
     var, cfg = api.device_batch(b)
-    plan = api.Plan(b.seg, k=8)
-    ws = api.Workspace(plan.workspace_bytes, cfg["seg"].device)
-    out = plan.score(arch, var, cfg, want_score=False, want_occ=False, workspace=ws)
+    dev = cfg["seg"].device
+    out = {"idx": torch.empty((1, 8), dtype=torch.int32, device=dev),
+           "val": torch.empty((1, 8), dtype=torch.float32, device=dev)}
+    shape, _ = api.autotune(arch, var, cfg, k=8, reps=20, outputs=out, want_score=False, want_occ=False)
+    plan = api.Plan(b.seg, k=8, shape=shape)
+    ws = api.Workspace(plan.workspace_bytes, dev)
     fn = lambda: plan.score(arch, var, cfg, want_score=False, want_occ=False, outputs=out, workspace=ws)
     ms_graph = _graph_time(fn, steps, warmup)
     ms_eager = _eager_time(fn, steps)

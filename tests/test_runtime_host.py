@@ -149,3 +149,31 @@ def test_parts_cover_and_assemble():
     other = dict(parts[1], seed=np.array([6]))
     with pytest.raises(ValueError):
         rd.assemble([parts[0], other])
+
+
+def test_imix_static_side_and_comparison(tmp_path):
+    from paper_1701_08547_amd import imix
+
+    cs = imix.cases()
+    assert len(cs) == 81 and len(set(cs)) == 81
+    pred = imix.predicted(cs, 256)
+    # a family's counted loads are at least one per element it reads
+    mv = [p for p in pred if p["family"] == "matvec" and p["U"] == 1]
+    for p in mv:
+        assert p["static"]["vmem_rd"] * 64 >= p["n"] * p["n"]
+    # a counter file that matches the static side exactly gives zero error
+    path = tmp_path / "c.csv"
+    with open(path, "w") as f:
+        f.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+        f.write('1,"void at::native::fill","SQ_INSTS_VALU",5\n')
+        for i, p in enumerate(pred):
+            kn = "void (anonymous namespace)::rt_%s<%d>(int)" % (p["family"], p["U"])
+            for cn, cls in imix.COUNTERS.items():
+                f.write('%d,"%s","%s",%d\n' % (i + 2, kn, cn, p["static"][cls]))
+            f.write('%d,"%s","SQ_WAVES",%d\n' % (i + 2, kn, p["waves"]))
+    rep = imix.compare(pred, imix.read_counters(str(path)))
+    for fam, s in rep["summary"].items():
+        assert s["waves_exact"]
+        assert all(v["max_abs_error"] == 0.0 for k, v in s.items() if k != "waves_exact")
+    with pytest.raises(ValueError):
+        imix.compare(pred[:-1], imix.read_counters(str(path)))
