@@ -4,12 +4,12 @@
  * harness.
  *
  * The paper tunes kernels by running every candidate configuration and
- * timing it (Sec. VI: one warm-up, ten timed runs, a fixed order statistic
+ * timing it (Sec. IV-A: one warm-up, ten timed runs, a fixed order statistic
  * kept); its static model exists to avoid that cost.  This library produces
  * such measurements for its own kernels so that a model correction can be
  * trained and judged on real runtimes: configurations are the paper's
  * tuning parameters block size T (threads per block) and unroll factor U
- * (Sec. V, Table IV), with the grid following from the problem size.
+ * (Sec. III-C, Table III), with the grid following from the problem size.
  *
  * Families (float32 data, problem size n):
  *   SA_RT_MATVEC   y += A x, A column-major n x n, n a multiple of 840, at
@@ -66,6 +66,25 @@ size_t sa_rt_buffer_floats(int32_t family, int64_t n, int32_t which);
 int32_t sa_rt_measure(int32_t family, int64_t n, const float *a, const float *b, float *c, const int32_t *T,
                       const int32_t *U, int32_t n_cfg, int32_t n_cu, int32_t warmup, int32_t reps, int32_t keep,
                       float *ms_out, void *stream);
+
+/* Issue cost of one instruction category of Eq. 6 on the current device,
+ * the counterpart of Table II (instructions per cycle per multiprocessor):
+ * a microbenchmark whose instruction stream is one category runs 32 waves
+ * (eight 256-thread workgroups) on every compute unit; cpi_out = elapsed
+ * cycles (peak clock) x compute units / thread-instructions of the category,
+ * i.e. CU-cycles per thread-instruction, from the median of `reps` (1..64)
+ * timed launches after one warm-up.  Categories:
+ *   SA_CPI_FP    v_fma_f32, eight independent chains
+ *   SA_CPI_INT   v_add_u32, eight independent chains
+ *   SA_CPI_MEM   global dword loads from a 16 KiB cache-resident buffer
+ *   SA_CPI_CTRL  a uniform loop branch (with its scalar counter)
+ *   SA_CPI_SYNC  workgroup barriers of four-wave workgroups
+ *   SA_CPI_REG   v_mov_b32
+ * buf: device buffer of at least 4,096 + 256 floats (read by SA_CPI_MEM; the
+ * tail is written only on an impossible result, which keeps the work live).
+ * ms_out (nullable): median launch time.  Synchronous. */
+enum { SA_CPI_FP = 0, SA_CPI_INT = 1, SA_CPI_MEM = 2, SA_CPI_CTRL = 3, SA_CPI_SYNC = 4, SA_CPI_REG = 5 };
+int32_t sa_rt_cpi(int32_t category, int32_t reps, float *buf, float *cpi_out, float *ms_out, void *stream);
 
 #ifdef __cplusplus
 }

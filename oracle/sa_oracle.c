@@ -16,7 +16,7 @@
  *     the configuration falls short of hiding latency (Eq. 2 discussion);
  *   - the k best configurations of each variant (the autotuner keeps the
  *     fastest variant, Sec. II-C; the static search ranks parameter
- *     coordinates, Sec. III-D).
+ *     coordinates, Sec. III-C).
  *
  * Readings where the paper is silent or garbled (all listed in the design
  * notes):

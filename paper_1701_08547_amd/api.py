@@ -39,7 +39,7 @@ EXPORTED = (
     "sa_plan_create", "sa_plan_destroy", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
-    "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure",
+    "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure", "sa_rt_cpi",
     "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
 )
 MLP_PARAMS = 20865
@@ -153,6 +153,8 @@ def lib():
             L.sa_rt_buffer_floats.restype = sz
             L.sa_rt_measure.argtypes = [i32, i64, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]
             L.sa_rt_measure.restype = i32
+            L.sa_rt_cpi.argtypes = [i32, i32, vp, vp, vp, vp]
+            L.sa_rt_cpi.restype = i32
             _lib = L
     return _lib
 

@@ -3,7 +3,7 @@ assembly the build writes (``sa_runtime_gfx950.s``).
 
 The paper derives its model inputs by statically analysing each kernel
 variant's machine code: instruction counts by category, registers and shared
-memory per thread block (Sec. IV-A, IV-C).  Here the same is done for the
+memory per thread block (Sec. III, Sec. IV-C).  Here the same is done for the
 measured kernel families, on AMD code objects built in this tree:
 
   * n_fp   vector floating-point arithmetic (f16/bf16/f32/f64 operations,

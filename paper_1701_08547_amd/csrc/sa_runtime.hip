@@ -9,7 +9,7 @@
 // read from the compiled code object scale with the trip counts computed on
 // the host.
 //
-// Timing follows the paper's experimental protocol (Sec. VI): one warm-up
+// Timing follows the paper's experimental protocol (Sec. IV-A): one warm-up
 // launch, then repeated timed launches of which a fixed order statistic is
 // kept (the fifth smallest of ten).
 #include <hip/hip_runtime.h>
@@ -136,6 +136,11 @@ int32_t rt_fail(int32_t code, const char *msg) {
 }
 
 }  // namespace
+
+// shared with the instruction-cost microbenchmarks (sa_cpi.hip)
+namespace sa_rt_detail {
+int32_t fail(int32_t code, const char *msg) { return rt_fail(code, msg); }
+}  // namespace sa_rt_detail
 
 extern "C" {
 

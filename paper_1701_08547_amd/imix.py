@@ -1,8 +1,8 @@
 """Static against dynamic instruction mix of the measured kernel families.
 
 The paper checks its statically derived instruction mix against the dynamic
-mix that hardware counters report for the same runs (Sec. V, the error
-rates of the instruction-mix metrics).  Here the static side is this
+mix that hardware counters report for the same runs (Sec. IV-B, the
+error rates of the instruction-mix metrics).  Here the static side is this
 library's own gfx950 assembly (asm_features: per-loop counts by the
 hardware's issue classes, times the host-computed trip counts, times the
 number of waves launched); the dynamic side is the per-dispatch SQ counters

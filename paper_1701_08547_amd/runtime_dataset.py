@@ -5,7 +5,7 @@ families built into the library (matvec, 5-point stencil, reduction; see
 ``include/sa_runtime.h``).  Each instance is timed at the 128 configurations
 T in {64, 128, ..., 1024} x U in {1, ..., 8} by the native harness with the
 paper's protocol (one warm-up launch, ten timed launches, the fifth smallest
-kept; Sec. VI).  Each (instance, configuration) row also gets the static
+kept; Sec. IV-A).  Each (instance, configuration) row also gets the static
 model's inputs, read from the family's own gfx950 code (asm_features):
 per-thread instruction counts (loop bodies times trip counts), registers,
 LDS bytes, a divergence share, block size, unroll factor and grid.

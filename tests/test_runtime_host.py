@@ -177,3 +177,25 @@ def test_imix_static_side_and_comparison(tmp_path):
         assert all(v["max_abs_error"] == 0.0 for k, v in s.items() if k != "waves_exact")
     with pytest.raises(ValueError):
         imix.compare(pred[:-1], imix.read_counters(str(path)))
+
+
+def test_cpi_argument_errors():
+    L = api.lib()
+    p = ctypes.c_void_p(256)
+    assert L.sa_rt_cpi(6, 3, p, p, None, None) == -1
+    assert L.sa_rt_cpi(-1, 3, p, p, None, None) == -1
+    assert L.sa_rt_cpi(0, 0, p, p, None, None) == -1
+    assert L.sa_rt_cpi(0, 65, p, p, None, None) == -1
+    assert L.sa_rt_cpi(0, 3, None, p, None, None) == -1
+    assert L.sa_rt_cpi(0, 3, p, None, None, None) == -1
+    assert b"NULL" in L.sa_rt_last_error()
+
+
+def test_calibrated_descriptor_mapping():
+    from paper_1701_08547_amd import calibration
+
+    arch = {"cpi_" + c: 1.0 for c in calibration.CATEGORIES}
+    meas = {c: (0.5 + i, 1.0) for i, c in enumerate(calibration.CATEGORIES)}
+    a = calibration.calibrated_arch(arch, meas)
+    assert a["cpi_fp"] == 0.5 and a["cpi_reg"] == 5.5 and a["cpi_sync"] == 4.5 / 4
+    assert arch["cpi_fp"] == 1.0                      # the input is not modified
