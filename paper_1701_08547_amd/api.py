@@ -41,6 +41,7 @@ EXPORTED = (
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure", "sa_rt_cpi",
     "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
+    "sa_product_workspace_bytes", "sa_score_product",
 )
 MLP_PARAMS = 20865
 MLP_FLAT = 20992
@@ -57,6 +58,11 @@ class SaVariants(ctypes.Structure):
 
 class SaConfigs(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in CONFIG_COLUMNS]
+
+
+class SaProduct(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("n_block", "n_unroll", "n_regs", "n_grid")] + \
+               [(f, ctypes.c_void_p) for f in ("block", "unroll", "regs", "grid")]
 
 
 class SaMlp(ctypes.Structure):
@@ -84,6 +90,11 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError("libsa.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+            # torch ships its own HIP runtime under the same soname as the
+            # system's: loading torch first makes the library bind to that one
+            # runtime.  Loaded the other way round, torch would run on the
+            # system runtime and find no device.
+            _torch()
             L = ctypes.CDLL(LIB_PATH)
             P, vp = ctypes.POINTER, ctypes.c_void_p
             i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -144,6 +155,11 @@ def lib():
             L.sa_score_suggested.restype = i32
             L.sa_headroom.argtypes = [P(SaArch), vp, vp, i64, vp, vp, vp]
             L.sa_headroom.restype = i32
+            L.sa_product_workspace_bytes.argtypes = [i64, i64, i32]
+            L.sa_product_workspace_bytes.restype = sz
+            L.sa_score_product.argtypes = [P(SaArch), P(SaVariants), i64, P(SaProduct), vp, vp, i32, vp, vp, vp, sz,
+                                           vp]
+            L.sa_score_product.restype = i32
             L.sa_rt_last_error.restype = ctypes.c_char_p
             L.sa_rt_grid.argtypes = [i32, i64, i32, i32, i32]
             L.sa_rt_grid.restype = i64
@@ -342,6 +358,58 @@ def suggest(arch: dict, variants: dict, out=None, stream=None):
     _check(lib().sa_suggest(ctypes.byref(a), ctypes.byref(_variants_struct(variants)), n_var,
                             _ptr(out, torch.int64, "kept"), _stream(stream)))
     return out
+
+
+PRODUCT_DIMS = ("block", "unroll", "regs", "grid")
+
+
+def product_size(space: dict) -> int:
+    """Configurations per variant of a product space (grid optional)."""
+    n = 1
+    for d in PRODUCT_DIMS:
+        if space.get(d) is not None:
+            n *= len(space[d])
+    return n
+
+
+def score_product(arch: dict, variants: dict, space: dict, k: int = 8, *, want_score: bool = True,
+                  want_occ: bool = True, want_topk: bool = True, outputs: dict | None = None,
+                  workspace: "Workspace | None" = None, stream=None) -> dict:
+    """sa_score over the product space `space` (dict of value lists for
+    block, unroll, regs and optionally grid; block slowest, grid fastest)
+    shared by every variant, without configuration rows (sa_score_product).
+    Per-evaluation outputs are indexed v * S + i."""
+    torch = _torch()
+    n_var = int(variants["n_fp"].shape[0])
+    dev = variants["n_fp"].device
+    S = product_size(space)
+    n = n_var * S
+    lists = {d: None if space.get(d) is None else np.ascontiguousarray(space[d], dtype=np.int32) for d in PRODUCT_DIMS}
+    ps = SaProduct(*[0 if lists[d] is None else int(lists[d].size) for d in PRODUCT_DIMS],
+                   *[None if lists[d] is None else lists[d].ctypes.data_as(ctypes.c_void_p) for d in PRODUCT_DIMS])
+    o = dict(outputs or {})
+    if want_occ and o.get("occ") is None:
+        o["occ"] = torch.empty(n, dtype=torch.int32, device=dev)
+    if want_score and o.get("score") is None:
+        o["score"] = torch.empty(n, dtype=torch.float32, device=dev)
+    if want_topk:
+        if o.get("idx") is None:
+            o["idx"] = torch.empty((n_var, k), dtype=torch.int32, device=dev)
+        if o.get("val") is None:
+            o["val"] = torch.empty((n_var, k), dtype=torch.float32, device=dev)
+    if workspace is None and want_topk:
+        workspace = Workspace(int(lib().sa_product_workspace_bytes(n_var, S, int(k))), dev)
+    for key in ("occ", "score", "idx", "val"):
+        o.setdefault(key, None)
+    a = _arch_struct(arch)
+    _check(lib().sa_score_product(ctypes.byref(a), ctypes.byref(_variants_struct(variants)), n_var, ctypes.byref(ps),
+                                  _ptr(o["score"] if want_score else None, torch.float32, "score"),
+                                  _ptr(o["occ"] if want_occ else None, torch.int32, "occ"), int(k),
+                                  _ptr(o["idx"] if want_topk else None, torch.int32, "idx"),
+                                  _ptr(o["val"] if want_topk else None, torch.float32, "val"),
+                                  workspace.ptr if workspace is not None else None,
+                                  workspace.nbytes if workspace is not None else 0, _stream(stream)))
+    return o
 
 
 def headroom(arch: dict, block, regs=None, stream=None):
