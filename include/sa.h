@@ -270,6 +270,38 @@ sa_status sa_suggest(const sa_arch *arch, const sa_variants *variants, int64_t n
                      void *stream);
 
 /*
+ * Search spaces that are full products (the autotuner's space of Sec. III-C,
+ * every tuning parameter taking each of its values): every variant is scored
+ * over the same S = n_block x n_unroll x n_regs x max(1, n_grid)
+ * configurations, and no configuration rows are stored.  Local index
+ * i = ((iT n_unroll + iU) n_regs + iR) max(1, n_grid) + iG (block slowest,
+ * grid fastest) stands for (block[iT], unroll[iU], regs[iR], grid[iG]); evaluation
+ * e = v S + i.  n_grid = 0: no grid dimension.  Value lists are host arrays,
+ * read during the call (each count at most SA_PRODUCT_MAX_VALUES, S at most
+ * SA_PRODUCT_MAX_SIZE).
+ */
+#define SA_PRODUCT_MAX_VALUES 64
+#define SA_PRODUCT_MAX_SIZE (1 << 24)
+typedef struct {
+  int32_t n_block, n_unroll, n_regs, n_grid;
+  const int32_t *block, *unroll, *regs, *grid;
+} sa_product;
+
+/* Workspace of sa_score_product with top-k output (bytes; 256-byte aligned
+ * device memory): fragment slots plus the implicit segment offsets. */
+size_t sa_product_workspace_bytes(int64_t n_variants, int64_t space_size, int32_t k);
+
+/* sa_score over the materialised product, without the rows: the same
+ * occupancy, score and top-k results (bit for bit) with score / occ_waves
+ * indexed by e = v S + i (n_variants * S entries) and top-k indices local.
+ * Errors as sa_score; an empty or oversized value list is SA_ERR_ARG.
+ * Asynchronous on `stream`; contents of the workspace need no
+ * initialisation. */
+sa_status sa_score_product(const sa_arch *arch, const sa_variants *variants, int64_t n_variants,
+                           const sa_product *space, float *score, int32_t *occ_waves, int32_t k, int32_t *topk_idx,
+                           float *topk_val, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Headroom at full occupancy (Sec. III-C; the R* and S* columns of Table VII):
  * for the block size T = block[i] of each row, the largest register count per
  * thread and the largest LDS per workgroup at which occupancy (Eqs. 1-5) is

@@ -187,3 +187,42 @@ def test_headroom_argument_errors(L):
     ctypes.memmove(ctypes.byref(bad), ctypes.byref(a), ctypes.sizeof(a))
     bad.wave_size = 48
     assert L.sa_headroom(ctypes.byref(bad), p(16), None, 4, p(16), None, None) == -6   # descriptor rejected
+
+
+def test_product_argument_errors(L):
+    a = api.SaArch()
+    assert L.sa_arch_gfx950(ctypes.byref(a)) == 0
+    v = api.SaVariants(*([16] * 9))
+    vals = (ctypes.c_int32 * 65)(*range(1, 66))
+    p = ctypes.cast(vals, ctypes.c_void_p)
+    out = ctypes.c_void_p(256)
+    ok = api.SaProduct(2, 2, 2, 0, p, p, p, None)
+    sc = lambda sp, **kw: L.sa_score_product(ctypes.byref(a), ctypes.byref(v), kw.get("n", 3),
+                                             None if sp is None else ctypes.byref(sp), kw.get("score", out), None,
+                                             kw.get("k", 8), kw.get("idx"), None, kw.get("ws"), kw.get("wsb", 0), None)
+    assert sc(None) == -1
+    assert sc(api.SaProduct(0, 2, 2, 0, p, p, p, None)) == -1            # empty block list
+    assert sc(api.SaProduct(65, 2, 2, 0, p, p, p, None)) == -1           # too many values
+    assert sc(api.SaProduct(2, 2, 2, -1, p, p, p, None)) == -1           # negative grid count
+    assert sc(api.SaProduct(2, 2, 2, 2, p, p, p, None)) == -1            # grid list NULL
+    assert sc(api.SaProduct(2, 2, 2, 0, p, None, p, None)) == -1        # unroll list NULL
+    assert sc(ok, n=-1) == -1
+    assert sc(ok, score=None) == -1                                     # no output
+    assert sc(ok, score=ctypes.c_void_p(258)) == -2                     # misaligned
+    assert sc(ok, idx=out, k=0) == -1                                   # k outside [1, 64]
+    assert sc(ok, idx=out, ws=None) == -4                               # top-k needs a workspace
+    assert sc(ok, idx=out, ws=ctypes.c_void_p(256), wsb=8) == -4        # too small
+    assert sc(ok, idx=out, ws=ctypes.c_void_p(128), wsb=1 << 20) == -2  # misaligned workspace
+    assert sc(ok, n=0) == 0
+    assert L.sa_product_workspace_bytes(3, 8, 8) > 0 and L.sa_product_workspace_bytes(0, 8, 8) == 0
+
+
+def test_product_division_bound():
+    """floor(x m / 2^32) with m = ceil(2^32 / n) is floor(x / n) for every
+    x < 2^24 and 2 <= n <= 64 (the digit extraction of product spaces)."""
+    import numpy as np
+
+    x = np.arange(1 << 24, dtype=np.uint64)
+    for n in range(2, 65):
+        m = np.uint64(((1 << 32) + n - 1) // n)
+        assert np.array_equal((x * m) >> np.uint64(32), x // np.uint64(n)), n
