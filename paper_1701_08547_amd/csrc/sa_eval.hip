@@ -68,6 +68,28 @@ __device__ __forceinline__ void buf_store(const T (&x)[N], __amdgpu_buffer_rsrc_
   }
 }
 
+// Values of a product space at local index li (Mode::Product): mixed-radix
+// digits, grid fastest.  floor(x / n) for x < 2^24 and n <= 256 is one
+// multiply-high by m = ceil(2^32 / n): with m n = 2^32 + r (r < n) and
+// x = q n + t, x m / 2^32 = q + t / n + x r / (n 2^32) < q + 1.  m = 0 stands
+// for n = 1.  Indices are clamped, so an index past the space reads a valid
+// value (such rows are masked out or never reached).
+struct ProductDigits {
+  const int32_t *pv;  // LDS: four lists of kProductMaxValues values
+  uint32_t nG, nR, nU, tmax;
+  uint32_t mG, mR, mU;
+  __device__ __forceinline__ static uint32_t div(uint32_t x, uint32_t m) { return m ? __umulhi(x, m) : x; }
+  __device__ __forceinline__ void at(uint32_t li, int32_t &T, int32_t &U, int32_t &R, int32_t &G) const {
+    const uint32_t q1 = div(li, mG);
+    const uint32_t q2 = div(q1, mR);
+    const uint32_t q3 = div(q2, mU);
+    T = pv[min(q3, tmax)];
+    U = pv[kProductMaxValues + (q2 - q3 * nU)];
+    R = pv[2 * kProductMaxValues + (q1 - q2 * nR)];
+    G = pv[3 * kProductMaxValues + (li - q1 * nG)];
+  }
+};
+
 // Streams one piece [e, pe) of one segment.  ITEMS consecutive evaluations
 // per lane per chunk (chunk = 64 ITEMS evaluations), one chunk of loads in
 // flight ahead of the one being evaluated.
@@ -79,6 +101,7 @@ struct Evaluator {
   const Piece &pc;
   Selector &sel;
   int lane;
+  ProductDigits pd{};
 
   // Masked rows over [base, end): lane l takes base + 64 i + l.  end - base <= 256.
   __device__ __forceinline__ void masked(int64_t base, int64_t end) {
@@ -90,7 +113,10 @@ struct Evaluator {
     for (int i = 0; i < 4; ++i) {
       const int j = lane + 64 * i;
       const bool in = j < rem;
-      if constexpr (MODE != Mode::Keys) {
+      if constexpr (MODE == Mode::Product) {
+        pd.at(in ? (uint32_t)(base + j - pc.s0) : 0u, Tv[i], Uv[i], Rv[i], Gv[i]);
+        if (!HAS_GRID) Gv[i] = 1;
+      } else if constexpr (MODE != Mode::Keys) {
         Tv[i] = in ? L.cfg.block[base + j] : 0;
         Uv[i] = in ? L.cfg.unroll[base + j] : 0;
         Rv[i] = in ? L.cfg.regs[base + j] : 0;
@@ -136,7 +162,14 @@ struct Evaluator {
   __device__ __forceinline__ Cols load_chunk(int64_t base) const {
     Cols c;
     const int lo = ITEMS * lane;
-    if constexpr (MODE != Mode::Keys) {
+    if constexpr (MODE == Mode::Product) {
+      const uint32_t li = (uint32_t)(base - pc.s0) + (uint32_t)lo;
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        pd.at(li + (uint32_t)i, c.T.v[i], c.U.v[i], c.R.v[i], c.G.v[i]);
+        if (!HAS_GRID) c.G.v[i] = 1;
+      }
+    } else if constexpr (MODE != Mode::Keys) {
       c.T = *(const IVec<ITEMS> *)((L.cfg.block + base) + lo);
       c.U = *(const IVec<ITEMS> *)((L.cfg.unroll + base) + lo);
       c.R = *(const IVec<ITEMS> *)((L.cfg.regs + base) + lo);
@@ -244,9 +277,20 @@ struct Evaluator {
 };
 
 
+// The product space travels as a kernel argument of the Product kernels only.
+struct NoProduct {};
+template <Mode MODE>
+struct ProductArg {
+  using type = NoProduct;
+};
+template <>
+struct ProductArg<Mode::Product> {
+  using type = KProduct;
+};
+
 template <Mode MODE, bool HAS_GRID, bool TOPK>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SA_WAVES_PER_EU)))
-void sa_eval_kernel(EvalLaunch L) {
+void sa_eval_kernel(EvalLaunch L, typename ProductArg<MODE>::type P) {
   // Dynamic LDS: the occupancy table [rg][W_B] followed by waves-by-registers
   // per register-granule count.
   extern __shared__ __align__(16) uint8_t dyn_lds[];
@@ -254,12 +298,20 @@ void sa_eval_kernel(EvalLaunch L) {
   __shared__ uint32_t tab_mwb[kMaxWB + 2];
   __shared__ uint8_t tab_blim[kMaxWB + 2];
   __shared__ WaveLds wl[kWavesPerBlock];
+  __shared__ int32_t pvals[MODE == Mode::Product ? 4 * kProductMaxValues : 1];
 
   const KArch &A = L.arch;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = tid / kWaveSize;
   (void)A;
+  if constexpr (MODE == Mode::Product) {
+    for (int i = tid; i < 4 * kProductMaxValues; i += kBlockThreads)
+      pvals[i] = P.vals[i / kProductMaxValues][i % kProductMaxValues];
+  } else {
+    (void)P;
+  }
+  // (the barrier at the end of build_tables also publishes pvals)
   if constexpr (MODE != Mode::Keys) build_tables(L, dyn_lds, tab_rcap, tab_mwb, tab_blim, tid, kBlockThreads);
   const uint8_t *tab_b = dyn_lds;
 
@@ -277,11 +329,22 @@ void sa_eval_kernel(EvalLaunch L) {
   sel.theta = kThetaInit;
   const Tables tb{tab_b, tab_rcap};
 
-  int64_t v = find_segment(seg, L.n_var, n_evals, t0, lane);
+  // product spaces: every segment has P.size evaluations, no offsets to read
+  int64_t v;
+  if constexpr (MODE == Mode::Product)
+    v = t0 / P.size;
+  else
+    v = find_segment(seg, L.n_var, n_evals, t0, lane);
   int64_t e = t0;
   for (; v < L.n_var && e < t1; ++v) {
-    const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
-    const int64_t s1 = uniform64(clamp_off(seg[v + 1], n_evals));
+    int64_t s0, s1;
+    if constexpr (MODE == Mode::Product) {
+      s0 = v * P.size;
+      s1 = s0 + P.size;
+    } else {
+      s0 = uniform64(clamp_off(seg[v], n_evals));
+      s1 = uniform64(clamp_off(seg[v + 1], n_evals));
+    }
     int64_t pe = s1 > e ? s1 : e;
     pe = pe < t1 ? pe : t1;
     if (pe <= e) continue;
@@ -296,6 +359,9 @@ void sa_eval_kernel(EvalLaunch L) {
       sel.theta = kThetaInit;
     }
     Evaluator<MODE, HAS_GRID, TOPK, 4> ev{L, tb, pc, sel, lane};
+    if constexpr (MODE == Mode::Product)
+      ev.pd = ProductDigits{pvals, (uint32_t)P.n[3], (uint32_t)P.n[2], (uint32_t)P.n[1],
+                            (uint32_t)P.n[0] - 1u, P.magic[0], P.magic[1], P.magic[2]};
     ev.run(e, pe);
 
     if constexpr (TOPK) {
@@ -524,7 +590,17 @@ hipError_t launch_one(const EvalLaunch &L, hipStream_t stream) {
   const int64_t blocks = (L.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return hipSuccess;
   const size_t dyn = M != Mode::Keys ? (size_t)L.dyn_lds_bytes : 0;
-  hipLaunchKernelGGL((sa_eval_kernel<M, G, K>), dim3((uint32_t)blocks), dim3(kBlockThreads), dyn, stream, L);
+  hipLaunchKernelGGL((sa_eval_kernel<M, G, K>), dim3((uint32_t)blocks), dim3(kBlockThreads), dyn, stream, L,
+                     NoProduct{});
+  return hipGetLastError();
+}
+
+template <bool G, bool K>
+hipError_t launch_one_product(const EvalLaunch &L, const KProduct &P, hipStream_t stream) {
+  const int64_t blocks = (L.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((sa_eval_kernel<Mode::Product, G, K>), dim3((uint32_t)blocks), dim3(kBlockThreads),
+                     (size_t)L.dyn_lds_bytes, stream, L, P);
   return hipGetLastError();
 }
 
@@ -542,6 +618,12 @@ hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk,
     return topk ? launch_one<Mode::Model, true, true>(L, stream) : launch_one<Mode::Model, true, false>(L, stream);
   }
   return topk ? launch_one<Mode::Model, false, true>(L, stream) : launch_one<Mode::Model, false, false>(L, stream);
+}
+
+hipError_t launch_product(const EvalLaunch &L, const KProduct &P, bool has_grid, bool topk, hipStream_t stream) {
+  if (has_grid)
+    return topk ? launch_one_product<true, true>(L, P, stream) : launch_one_product<true, false>(L, P, stream);
+  return topk ? launch_one_product<false, true>(L, P, stream) : launch_one_product<false, false>(L, P, stream);
 }
 
 hipError_t launch_plan(const EvalLaunch &L, const PlanDev &P, const PlanShape &S, Mode mode, bool has_grid, bool topk,

@@ -64,8 +64,20 @@ struct EvalLaunch {
 };
 
 // Model: score the configurations; Keys: select over given keys; Suggest:
-// score, selecting only within the paper's reduced search space.
-enum class Mode { Model, Keys, Suggest };
+// score, selecting only within the paper's reduced search space; Product:
+// score a product space shared by every variant, values derived from each
+// evaluation's local index instead of loaded.
+enum class Mode { Model, Keys, Suggest, Product };
+
+// A product space for Mode::Product: value lists of block, unroll, registers
+// and grid (a count of 1 and value 1 without a grid), grid fastest.
+constexpr int kProductMaxValues = 64;
+struct KProduct {
+  int32_t n[4];
+  uint32_t magic[3];  // ceil(2^32 / n) for grid, registers, unroll; 0 when n = 1
+  int32_t size;       // n[0] n[1] n[2] n[3]
+  int32_t vals[4][kProductMaxValues];
+};
 
 // A plan cuts a CSR batch into workgroup items.  kind 0: whole segments
 // [v0, v1) per wave.  kind 1: one segment's range split into one part per
@@ -149,6 +161,7 @@ hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, c
                              TrainBufs T, AdamArgs h, float *grad_out, hipStream_t stream);
 
 hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream);
+hipError_t launch_product(const EvalLaunch &L, const KProduct &P, bool has_grid, bool topk, hipStream_t stream);
 hipError_t launch_plan(const EvalLaunch &L, const PlanDev &P, const PlanShape &S, Mode mode, bool has_grid, bool topk,
                        int n_cu, hipStream_t stream);
 hipError_t launch_split_merge(const EvalLaunch &L, const PlanDev &P, hipStream_t stream);
