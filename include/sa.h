@@ -349,7 +349,8 @@ sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_
                                   void *workspace, size_t workspace_bytes, void *stream);
 
 /* Tile size (evaluations per wave) the next sa_score / sa_occupancy /
- * sa_topk calls on this thread use; 0 restores the library's choice.  Must
+ * sa_topk / sa_score_product calls on this thread use; 0 restores the
+ * library's choice.  Must
  * be a multiple of 256 in [1024, 65536]. */
 sa_status sa_set_tile(int32_t evals_per_wave);
 

@@ -113,6 +113,8 @@ sa::KArch to_karch(const sa_arch *a) {
   return k;
 }
 
+int32_t tile_override() { return g_tile; }
+
 int32_t pick_tile(int64_t n_evals) {
   if (g_tile > 0) return g_tile;
   (void)n_evals;
