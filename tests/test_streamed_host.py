@@ -39,3 +39,11 @@ def test_c4_recipe():
     assert 1.2e10 < b.n_evals < 1.35e10
     sub = b.subset([3, 99999])
     assert sub.n_evals == sizes[3] + sizes[99999]
+
+
+def test_generator_reference_sequence(golden):
+    """The counter-based reading of SplitMix64 (output k = state after k + 1
+    steps, finalised) reproduces the generator's published sequence."""
+    g = golden("splitmix64.json")
+    got = workloads.splitmix64_at(g["state"], np.arange(len(g["outputs"])))
+    assert [int(x) for x in got] == g["outputs"]
