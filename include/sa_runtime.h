@@ -7,7 +7,7 @@
  * timing it (Sec. IV-A: one warm-up, ten timed runs, a fixed order statistic
  * kept); its static model exists to avoid that cost.  This library produces
  * such measurements for its own kernels so that a model correction can be
- * trained and judged on real runtimes: configurations are the paper's
+ * trained and assessed on real runtimes: configurations are the paper's
  * tuning parameters block size T (threads per block) and unroll factor U
  * (Sec. III-C, Table III), with the grid following from the problem size.
  *
