@@ -294,7 +294,8 @@ size_t sa_product_workspace_bytes(int64_t n_variants, int64_t space_size, int32_
 /* sa_score over the materialised product, without the rows: the same
  * occupancy, score and top-k results (bit for bit) with score / occ_waves
  * indexed by e = v S + i (n_variants * S entries) and top-k indices local.
- * Errors as sa_score; an empty or oversized value list is SA_ERR_ARG.
+ * Errors as sa_score; an empty or oversized value list is SA_ERR_ARG; with
+ * n_variants = 0 the call only checks the descriptor and the space.
  * Asynchronous on `stream`; contents of the workspace need no
  * initialisation. */
 sa_status sa_score_product(const sa_arch *arch, const sa_variants *variants, int64_t n_variants,

@@ -86,13 +86,13 @@ sa_status sa_score_product(const sa_arch *arch, const sa_variants *variants, int
   }
   if (S > SA_PRODUCT_MAX_SIZE) return fail(SA_ERR_ARG, "space of %lld configurations exceeds %d", (long long)S,
                                            SA_PRODUCT_MAX_SIZE);
+  if (n_variants == 0) return SA_OK;  // nothing to write (outputs of an empty batch may be NULL)
   const bool topk = topk_idx || topk_val;
   if (topk && (k < 1 || k > SA_K_MAX)) return fail(SA_ERR_ARG, "k = %d outside [1, %d]", k, SA_K_MAX);
   if (!topk && !score && !occ_waves) return fail(SA_ERR_ARG, "no output requested");
   const void *outs[] = {score, occ_waves, topk_idx, topk_val};
   for (const void *p : outs)
     if (p && !aligned(p, 4)) return fail(SA_ERR_ALIGN, "output not 4-byte aligned");
-  if (n_variants == 0) return SA_OK;
 
   sa::KProduct P{};
   for (int d = 0; d < 4; ++d) {

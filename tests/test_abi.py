@@ -208,6 +208,7 @@ def test_product_argument_errors(L):
     assert sc(api.SaProduct(2, 2, 2, 0, p, None, p, None)) == -1        # unroll list NULL
     assert sc(ok, n=-1) == -1
     assert sc(ok, score=None) == -1                                     # no output
+    assert sc(ok, n=0, score=None) == 0                                 # empty batch: nothing to write
     assert sc(ok, score=ctypes.c_void_p(258)) == -2                     # misaligned
     assert sc(ok, idx=out, k=0) == -1                                   # k outside [1, 64]
     assert sc(ok, idx=out, ws=None) == -4                               # top-k needs a workspace

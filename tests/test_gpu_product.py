@@ -119,3 +119,36 @@ def test_product_full_size_benchmark_space():
     assert_same(ref, got)
     del var, cfg, ref, got
     torch.cuda.empty_cache()
+
+
+def test_product_maximum_space_and_k():
+    """The largest space (64 values in each of the four lists, 2^24
+    configurations) with k = 64: equal to the materialised pass."""
+    arch = oracle.arch_cdna4()
+    v = workloads.variant_features(1, 905)
+    g = np.random.default_rng(905)
+    space = {"block": np.sort(g.choice(np.arange(1, 1100), 64, replace=False)).astype(np.int32),
+             "unroll": np.arange(1, 65, dtype=np.int32),
+             "regs": np.sort(g.choice(np.arange(0, 530), 64, replace=False)).astype(np.int32),
+             "grid": (np.arange(1, 65) * 97).astype(np.int32)}
+    assert api.product_size(space) == 1 << 24
+    b, ref, got = run_both(arch, v, space, 64)
+    say("maximum space", b.n_evals, "legal top-64 of", int((ref["idx"].cpu().numpy() >= 0).sum()))
+    assert_same(ref, got)
+    del ref, got
+    torch.cuda.empty_cache()
+
+
+def test_product_empty_and_limits():
+    arch = oracle.arch_cdna4()
+    v = workloads.variant_features(0, 906)
+    var = api.device_batch(workloads.Batch(v, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                                           np.zeros(0, np.int32), None, "p"))[0]
+    out = api.score_product(arch, var, SPACE_GRID, k=8)
+    torch.cuda.synchronize()
+    assert out["idx"].shape == (0, 8) and out["occ"].numel() == 0
+    v = workloads.variant_features(2, 907)
+    var = api.device_batch(workloads.Batch(v, np.zeros(3, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                                           np.zeros(0, np.int32), None, "p"))[0]
+    with pytest.raises(api.SAError):
+        api.score_product(arch, var, {"block": list(range(1, 66)), "unroll": [1], "regs": [0]}, k=8)
