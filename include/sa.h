@@ -349,6 +349,21 @@ sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_
                                   float lr, const float *feat, const float *target, int64_t n, float *grad_out,
                                   void *workspace, size_t workspace_bytes, void *stream);
 
+/* The same step with a pairwise ranking loss instead of squared error (the
+ * correction's purpose is the order of configurations, Sec. III-C): rows come
+ * in groups of `group` consecutive rows (one kernel instance's
+ * configurations; n a multiple of group, group in [2, SA_RANK_GROUP_MAX]).
+ * With z = feat[.][22] (ln score, as computed by sa_features) + Delta, every
+ * ordered pair (i, j) of a group with log_time[i] < log_time[j] costs
+ * softplus(z_i - z_j) = ln(1 + e^(z_i - z_j)); the loss is the mean over each
+ * group's pairs, averaged over the groups (a group of equal times adds 0).
+ * grad_out's loss entry is that loss. */
+#define SA_RANK_GROUP_MAX 1024
+sa_status sa_surrogate_train_step_pairwise(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v,
+                                           int64_t step, float lr, const float *feat, const float *log_time,
+                                           int64_t n, int32_t group, float *grad_out, void *workspace,
+                                           size_t workspace_bytes, void *stream);
+
 /* Tile size (evaluations per wave) the next sa_score / sa_occupancy /
  * sa_topk / sa_score_product calls on this thread use; 0 restores the
  * library's choice.  Must

@@ -16,7 +16,11 @@ Definitions (shared with the GPU only through these written rules):
   * h1 = bf16(GELU(W1 x + b1)), h2 = bf16(GELU(W2 h1 + b2)), Delta = w3 . h2 + b3
     with W1 128x32, W2 128x128, w3 128 (bfloat16 values), b1, b2 (128) and b3
     float; GELU(a) = a/2 (1 + erf(a / sqrt 2));
-  * loss = mean over the batch of (Delta - r)^2;
+  * loss = mean over the batch of (Delta - r)^2, or the pairwise ranking loss
+    (``pairwise_loss``): within each group of consecutive rows (one kernel
+    instance), every ordered pair (i, j) with measured y_i < y_j costs
+    softplus(z_i - z_j), z = ln score + Delta; mean over each group's pairs,
+    averaged over the groups;
   * Adam(lr, beta1, beta2, eps) on float master weights.
 
 The backward pass treats the bf16 rounding of h1 and h2 as the identity (the
@@ -139,7 +143,51 @@ def loss_and_grads(p: dict, x: np.ndarray, r: np.ndarray, quantise: bool = True)
     B = x.shape[0]
     d = fw["delta"] - np.asarray(r, np.float64)
     loss = float(np.mean(d * d))
-    g_delta = 2.0 * d / B
+    return loss, backward(fw, x, 2.0 * d / B), fw
+
+
+def softplus(x):
+    x = np.asarray(x, np.float64)
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-np.asarray(x, np.float64)))
+
+
+def pairwise_loss(z: np.ndarray, y: np.ndarray, group: int):
+    """Pairwise ranking loss over groups of `group` consecutive rows and its
+    gradient with respect to z, in binary64, pair by pair."""
+    z = np.asarray(z, np.float64)
+    y = np.asarray(y, np.float64)
+    n = z.size
+    n_groups = n // group
+    loss, g = 0.0, np.zeros(n)
+    for b in range(n_groups):
+        lo = b * group
+        pairs = [(i, j) for i in range(lo, lo + group) for j in range(lo, lo + group) if y[i] < y[j]]
+        if not pairs:
+            continue
+        w = 1.0 / (n_groups * len(pairs))
+        for i, j in pairs:
+            loss += w * softplus(z[i] - z[j])
+            s = sigmoid(z[i] - z[j])
+            g[i] += w * s
+            g[j] -= w * s
+    return float(loss), g
+
+
+def ranking_loss_and_grads(p: dict, x: np.ndarray, ln_score: np.ndarray, y: np.ndarray, group: int,
+                           quantise: bool = True):
+    """Pairwise ranking loss of z = ln_score + Delta and its gradients with
+    respect to every parameter."""
+    fw = forward(p, x, quantise)
+    loss, g_delta = pairwise_loss(np.asarray(ln_score, np.float64) + fw["delta"], y, group)
+    return loss, backward(fw, x, g_delta), fw
+
+
+def backward(fw: dict, x: np.ndarray, g_delta: np.ndarray) -> dict:
+    """Gradients of every parameter from dL/dDelta per row."""
     g = {}
     g["w3"] = fw["h2"].T @ g_delta
     g["b3"] = np.array([g_delta.sum()])
@@ -151,7 +199,7 @@ def loss_and_grads(p: dict, x: np.ndarray, r: np.ndarray, quantise: bool = True)
     g_a1 = g_h1 * gelu_grad(fw["a1"])
     g["W1"] = g_a1.T @ x
     g["b1"] = g_a1.sum(0)
-    return loss, g, fw
+    return g
 
 
 def adam_step(p: dict, g: dict, state: dict, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8) -> dict:

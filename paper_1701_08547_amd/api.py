@@ -38,7 +38,7 @@ EXPORTED = (
     "sa_workspace_bytes", "sa_occupancy", "sa_score", "sa_topk", "sa_set_tile",
     "sa_plan_create", "sa_plan_destroy", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
-    "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step",
+    "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step", "sa_surrogate_train_step_pairwise",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure", "sa_rt_cpi",
     "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
     "sa_product_workspace_bytes", "sa_score_product",
@@ -146,6 +146,9 @@ def lib():
             L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64, vp, vp, sz,
                                                   vp]
             L.sa_surrogate_train_step.restype = i32
+            L.sa_surrogate_train_step_pairwise.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64,
+                                                           i32, vp, vp, sz, vp]
+            L.sa_surrogate_train_step_pairwise.restype = i32
             L.sa_gen_configs.argtypes = [ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp]
             L.sa_gen_configs.restype = i32
             L.sa_suggest.argtypes = [P(SaArch), P(SaVariants), i64, vp, vp]
@@ -706,8 +709,12 @@ class Surrogate:
                                       _ptr(out, torch.float32, "out"), _stream(stream)))
         return out
 
-    def train_step(self, feat, target, lr: float = 1e-3, stream=None):
-        """One Adam step on the batch; returns the batch loss (0-d device tensor)."""
+    def train_step(self, feat, target, lr: float = 1e-3, stream=None, group: int = 0):
+        """One Adam step on the batch; returns the batch loss (0-d device
+        tensor).  group = 0: squared error against `target` (the residual);
+        group > 0: pairwise ranking loss over groups of `group` consecutive
+        rows with `target` the measured log runtime
+        (sa_surrogate_train_step_pairwise)."""
         torch = _torch()
         n = int(feat.shape[0])
         need = int(lib().sa_surrogate_train_workspace_bytes(n))
@@ -715,11 +722,15 @@ class Surrogate:
             self._ws = Workspace(need, self.device)
         ws_ptr, ws_bytes = (self._ws.ptr, self._ws.nbytes) if self._ws is not None else (None, 0)
         m = self.struct()
-        _check(lib().sa_surrogate_train_step(ctypes.byref(m), _ptr(self.master, torch.float32),
-                                             _ptr(self.m, torch.float32), _ptr(self.v, torch.float32),
-                                             self.step_count + 1, float(lr), _ptr(feat, torch.float32, "feat"),
-                                             _ptr(target, torch.float32, "target"), n,
-                                             _ptr(self.grad, torch.float32), ws_ptr, ws_bytes, _stream(stream)))
+        common = (ctypes.byref(m), _ptr(self.master, torch.float32), _ptr(self.m, torch.float32),
+                  _ptr(self.v, torch.float32), self.step_count + 1, float(lr), _ptr(feat, torch.float32, "feat"),
+                  _ptr(target, torch.float32, "target"), n)
+        if group > 0:
+            _check(lib().sa_surrogate_train_step_pairwise(*common, int(group), _ptr(self.grad, torch.float32), ws_ptr,
+                                                          ws_bytes, _stream(stream)))
+        else:
+            _check(lib().sa_surrogate_train_step(*common, _ptr(self.grad, torch.float32), ws_ptr, ws_bytes,
+                                                 _stream(stream)))
         self.step_count += 1
         return self.grad[MLP_PARAMS]
 

@@ -108,6 +108,15 @@ def search_regret(key: np.ndarray, t: np.ndarray, k: int):
     return float(t[order].min() / t.min() - 1.0), float(t[order].sum() / t.sum())
 
 
+def random_search_regret(t: np.ndarray, k: int, draws: int, g: np.random.Generator):
+    """The same budget spent on k configurations drawn at random (without
+    replacement): mean regret and mean time share over `draws` draws."""
+    n = t.size
+    picks = np.argsort(g.random((draws, n)), axis=1)[:, :k]
+    sel = t[picks]
+    return float((sel.min(axis=1) / t.min() - 1.0).mean()), float((sel.sum(axis=1) / t.sum()).mean())
+
+
 def bootstrap_ci(x: np.ndarray, reps: int = 2000, seed: int = 0):
     g = np.random.default_rng(seed)
     m = np.array([g.choice(x, x.size).mean() for _ in range(reps)])
@@ -126,10 +135,12 @@ def init_params(seed: int) -> dict:
 
 
 def train(feat, target, mean, inv_std, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
-          device="cuda", log=None):
-    """Adam on MSE(Delta, r) over shuffled mini-batches (device tensors feat
-    [n, 24] and target [n]); returns the Surrogate and the per-epoch mean
-    loss."""
+          device="cuda", log=None, group: int = 0):
+    """Adam over shuffled mini-batches (device tensors feat [n, 24] and
+    target [n]); returns the Surrogate and the per-epoch mean loss.
+    group = 0: MSE(Delta, r) with rows shuffled; group > 0: the pairwise
+    ranking loss with target the log runtime, whole groups of `group`
+    consecutive rows (one instance each) shuffled as units."""
     import torch
 
     sur = api.Surrogate(init_params(seed), mean, inv_std, device)
@@ -137,15 +148,21 @@ def train(feat, target, mean, inv_std, epochs: int = 40, batch: int = 4096, lr: 
     gen = torch.Generator(device=device)
     gen.manual_seed(170108547 + seed)
     losses = []
+    if group > 0:
+        batch = max(group, batch // group * group)
     for ep in range(epochs):
-        perm = torch.randperm(n, generator=gen, device=device)
+        if group > 0:
+            g_perm = torch.randperm(n // group, generator=gen, device=device)
+            perm = (g_perm[:, None] * group + torch.arange(group, device=device)[None, :]).reshape(-1)
+        else:
+            perm = torch.randperm(n, generator=gen, device=device)
         tot = torch.zeros((), dtype=torch.float32, device=device)
         nb = 0
         for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
             idx = perm[b0:b0 + batch]
             fb = feat.index_select(0, idx).contiguous()
             tb = target.index_select(0, idx).contiguous()
-            tot += sur.train_step(fb, tb, lr=lr)
+            tot += sur.train_step(fb, tb, lr=lr, group=group)
             nb += 1
         losses.append(float(tot.item()) / max(1, nb))
         if log:
@@ -186,12 +203,16 @@ def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, 
                "regret_diff_ci": bootstrap_ci(rp - rc),
                "spearman_plain": float(sp.mean()), "spearman_corrected": float(sc.mean())}
         search = {}
+        g = np.random.default_rng(np.random.SeedSequence([170108547, 3, 400]))
         for k in SEARCH_K:
             p = np.array([search_regret(ln_s[i], ms[i], k) for i in ids])
             c = np.array([search_regret(z[i], ms[i], k) for i in ids])
+            rnd = np.array([random_search_regret(ms[i], k, 32, g) for i in ids])
             search[str(k)] = {"regret_plain": float(p[:, 0].mean()), "regret_corrected": float(c[:, 0].mean()),
+                              "regret_random": float(rnd[:, 0].mean()),
                               "time_share_plain": float(p[:, 1].mean()),
-                              "time_share_corrected": float(c[:, 1].mean())}
+                              "time_share_corrected": float(c[:, 1].mean()),
+                              "time_share_random": float(rnd[:, 1].mean())}
         out["search"] = search
         if pruned is not None:
             out["pruned_fraction"] = float(1.0 - pruned[ids].mean())
@@ -208,7 +229,8 @@ def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, 
     return rep
 
 
-def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0, device="cuda", log=None):
+def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0, device="cuda", log=None,
+        loss: str = "mse"):
     import torch
 
     n_inst = int(data["instance"].max()) + 1
@@ -230,9 +252,17 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     inv = np.where(sd > 1e-12, 1.0 / np.maximum(sd, 1e-12), 1.0).astype(np.float32)
     idx = torch.from_numpy(rows_tr).to(device)
     f_tr = feat.index_select(0, idx).contiguous()
-    r_tr = torch.from_numpy(r.reshape(-1)[rows_tr].astype(np.float32)).to(device)
+    if loss == "pairwise":
+        # whole instances (128 consecutive rows each), targets the log runtimes
+        r_tr = torch.from_numpy(np.log(ms).reshape(-1)[rows_tr].astype(np.float32)).to(device)
+        group = N_CFG
+    elif loss == "mse":
+        r_tr = torch.from_numpy(r.reshape(-1)[rows_tr].astype(np.float32)).to(device)
+        group = 0
+    else:
+        raise ValueError("loss must be 'mse' or 'pairwise'")
     t0 = time.time()
-    sur, losses = train(f_tr, r_tr, mean, inv, epochs, batch, lr, seed, device, log)
+    sur, losses = train(f_tr, r_tr, mean, inv, epochs, batch, lr, seed, device, log, group=group)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     z = corrected_keys(feat, sur).cpu().numpy().astype(np.float64).reshape(n_inst, N_CFG)
@@ -242,7 +272,7 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     j = np.clip(T // ws - 1, 0, 63).astype(np.uint64)
     pruned = ((T % ws == 0) & (((kept >> j) & np.uint64(1)) == 1)).reshape(n_inst, N_CFG)
     rep = evaluate(ms, ln_s, z, held, families, pruned)
-    rep["train"] = {"rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
+    rep["train"] = {"loss": loss, "rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
                     "loss_first": losses[0], "loss_last": losses[-1],
                     "target_var": float(np.var(r.reshape(-1)[rows_tr]))}
     return sur, rep
@@ -257,12 +287,13 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--loss", choices=("mse", "pairwise"), default="mse")
     ap.add_argument("--out", default=None, help="npz of the trained network state")
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     data = load(a.data) if a.data else runtime_dataset.assemble(a.parts)
-    sur, rep = run(data, a.epochs, a.batch, a.lr, a.seed, log=log)
+    sur, rep = run(data, a.epochs, a.batch, a.lr, a.seed, log=log, loss=a.loss)
     if a.out:
         np.savez(a.out, **{k: np.asarray(v) for k, v in sur.state_dict().items()})
     txt = json.dumps(rep, indent=1)

@@ -157,8 +157,10 @@ hipError_t launch_headroom(const EvalLaunch &L, const int32_t *block, const int3
 hipError_t launch_corrected(const EvalLaunch &L, const MlpDev &M, bool has_grid, hipStream_t stream);
 hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream);
 int64_t train_slabs(int64_t n);
+// group = 0: squared error against target; group > 0: pairwise ranking loss
+// over groups of `group` consecutive rows with target = log runtime.
 hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,
-                             TrainBufs T, AdamArgs h, float *grad_out, hipStream_t stream);
+                             TrainBufs T, AdamArgs h, float *grad_out, int32_t group, hipStream_t stream);
 
 hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream);
 hipError_t launch_product(const EvalLaunch &L, const KProduct &P, bool has_grid, bool topk, hipStream_t stream);

@@ -327,6 +327,49 @@ __global__ __launch_bounds__(kMlpThreads) void sa_train_fwd_kernel(MlpDev M, con
   }
 }
 
+// Pairwise ranking loss, one workgroup per group of `group` consecutive rows
+// (one kernel instance's configurations).  z = ln score (feature 22, raw) +
+// Delta is the corrected key; every ordered pair (i, j) with y_i < y_j (y the
+// measured log runtime) costs softplus(z_i - z_j), and the loss is the mean
+// over pairs within each group, averaged over the groups.  dL/dz_i =
+// (sum over j after i of sigma(z_i - z_j) - sum over j before i of
+// sigma(z_j - z_i)) / (groups x pairs of the group); dL/dDelta = dL/dz.
+// Overwrites the squared-error terms the forward kernel left.
+__global__ __launch_bounds__(256) void sa_train_rank_kernel(const float *feat, const float *target, int32_t group,
+                                                            float inv_groups, TrainBufs T) {
+  extern __shared__ float zy[];  // z[group], y[group]
+  __shared__ int pairs;
+  const int64_t g0 = (int64_t)blockIdx.x * group;
+  if (threadIdx.x == 0) pairs = 0;
+  for (int i = threadIdx.x; i < group; i += blockDim.x) {
+    zy[i] = feat[(g0 + i) * kF + 22] + T.delta[g0 + i];
+    zy[group + i] = target[g0 + i];
+  }
+  __syncthreads();
+  int mine = 0;
+  for (int i = threadIdx.x; i < group; i += blockDim.x)
+    for (int j = 0; j < group; ++j) mine += zy[group + i] < zy[group + j] ? 1 : 0;
+  atomicAdd(&pairs, mine);
+  __syncthreads();
+  const float w = pairs > 0 ? inv_groups / (float)pairs : 0.0f;
+  for (int i = threadIdx.x; i < group; i += blockDim.x) {
+    const float zi = zy[i], yi = zy[group + i];
+    float g = 0.0f, l = 0.0f;
+    for (int j = 0; j < group; ++j) {
+      const float zj = zy[j], yj = zy[group + j];
+      if (yi < yj) {
+        const float x = zi - zj;
+        g += 1.0f / (1.0f + expf(-x));
+        l += fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+      } else if (yj < yi) {
+        g -= 1.0f / (1.0f + expf(zi - zj));
+      }
+    }
+    T.gdelta[g0 + i] = g * w;
+    T.sq[g0 + i] = l * w;
+  }
+}
+
 // Per row: dA2 = (dDelta w3) * GELU'(a2), dH1 = dA2 W2 (MFMA), dA1 = dH1 *
 // GELU'(a1); dA2, dA1 stored bf16 for the weight-gradient contractions.
 __global__ __launch_bounds__(kMlpThreads) void sa_train_bwd_rows_kernel(MlpDev M, int64_t n, TrainBufs T) {
@@ -515,7 +558,7 @@ hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *
 int64_t train_slabs(int64_t n) { return (n + kSlab - 1) / kSlab; }
 
 hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,
-                             TrainBufs T, AdamArgs h, float *grad_out, hipStream_t stream) {
+                             TrainBufs T, AdamArgs h, float *grad_out, int32_t group, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const int64_t n_blocks = (n + kRows - 1) / kRows;
   int64_t grid = (n_blocks + kMlpWaves - 1) / kMlpWaves;
@@ -523,6 +566,12 @@ hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, c
   hipLaunchKernelGGL(sa_train_fwd_kernel, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, feat, target, n, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (group > 0) {
+    const int64_t groups = n / group;
+    hipLaunchKernelGGL(sa_train_rank_kernel, dim3((uint32_t)groups), dim3(256), (size_t)(2 * group) * sizeof(float),
+                       stream, feat, target, group, 1.0f / (float)groups, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(sa_train_bwd_rows_kernel, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, n, T);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t slabs = train_slabs(n);

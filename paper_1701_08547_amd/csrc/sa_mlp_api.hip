@@ -107,9 +107,13 @@ size_t sa_surrogate_train_workspace_bytes(int64_t n) {
   return train_layout(n).total;
 }
 
-sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step,
-                                  float lr, const float *feat, const float *target, int64_t n, float *grad_out,
-                                  void *workspace, size_t workspace_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+sa_status train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step, float lr,
+                     const float *feat, const float *target, int64_t n, float *grad_out, int32_t group,
+                     void *workspace, size_t workspace_bytes, void *stream) {
   sa_status st;
   if ((st = check_mlp(mlp)) != SA_OK) return st;
   if (!master || !adam_m || !adam_v || !feat || !target) return fail(SA_ERR_ARG, "NULL argument");
@@ -140,10 +144,32 @@ sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_
   h.eps = 1e-8f;
   h.bc1 = (float)(1.0 - pow(0.9, (double)step));
   h.bc2 = (float)(1.0 - pow(0.999, (double)step));
-  h.inv_n = 1.0f / (float)n;
+  // the ranking loss's per-row terms already carry its normalisation
+  h.inv_n = group > 0 ? 1.0f : 1.0f / (float)n;
   hipError_t e = sa::launch_train_step(mlp_dev(mlp), sa::TrainState{master, adam_m, adam_v}, feat, target, n, T, h,
-                                       grad_out, (hipStream_t)stream);
+                                       grad_out, group, (hipStream_t)stream);
   return e == hipSuccess ? SA_OK : hip_fail(e, "training kernels launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step,
+                                  float lr, const float *feat, const float *target, int64_t n, float *grad_out,
+                                  void *workspace, size_t workspace_bytes, void *stream) {
+  return train_step(mlp, master, adam_m, adam_v, step, lr, feat, target, n, grad_out, 0, workspace, workspace_bytes,
+                    stream);
+}
+
+sa_status sa_surrogate_train_step_pairwise(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v,
+                                           int64_t step, float lr, const float *feat, const float *log_time,
+                                           int64_t n, int32_t group, float *grad_out, void *workspace,
+                                           size_t workspace_bytes, void *stream) {
+  if (group < 2 || group > SA_RANK_GROUP_MAX) return fail(SA_ERR_ARG, "group %d outside [2, %d]", group, SA_RANK_GROUP_MAX);
+  if (n % group != 0) return fail(SA_ERR_ARG, "n = %lld is not a multiple of group %d", (long long)n, group);
+  return train_step(mlp, master, adam_m, adam_v, step, lr, feat, log_time, n, grad_out, group, workspace,
+                    workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -227,3 +227,14 @@ def test_product_division_bound():
     for n in range(2, 65):
         m = np.uint64(((1 << 32) + n - 1) // n)
         assert np.array_equal((x * m) >> np.uint64(32), x // np.uint64(n)), n
+
+
+def test_pairwise_train_argument_errors(L):
+    m = api.SaMlp(*([ctypes.c_void_p(256)] * 8))
+    p = ctypes.c_void_p(256)
+    call = lambda n, group: L.sa_surrogate_train_step_pairwise(ctypes.byref(m), p, p, p, 1, ctypes.c_float(1e-3), p, p,
+                                                               n, group, None, p, 1 << 30, None)
+    assert call(256, 1) == -1           # group below 2
+    assert call(2048, 2048) == -1       # group above the maximum
+    assert call(300, 128) == -1         # n not a multiple of the group
+    assert b"group" in L.sa_last_error() or b"multiple" in L.sa_last_error()

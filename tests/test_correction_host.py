@@ -55,3 +55,13 @@ def test_search_regret_hand_case():
     for _ in range(20):
         k2, t2 = g.random(128), g.random(128) + 0.1
         assert correction.search_regret(k2, t2, 1)[0] == correction.regret(k2, t2)
+
+
+def test_random_search_regret():
+    g = np.random.default_rng(0)
+    t = np.array([1.0, 2.0, 3.0, 4.0])
+    r, share = correction.random_search_regret(t, 4, 16, g)
+    assert r == 0.0 and abs(share - 1.0) < 1e-12          # every configuration timed
+    r1, s1 = correction.random_search_regret(t, 1, 20000, g)
+    assert abs(r1 - (0 + 1 + 2 + 3) / 4) < 0.05          # mean regret of one random pick
+    assert abs(s1 - 0.25) < 0.01

@@ -213,3 +213,58 @@ def test_surrogate_errors():
         s.train_step(f, torch.zeros(4, device="cuda"), lr=0.0)
     with pytest.raises(api.SAError):
         s.train_step(f, torch.zeros(4, device="cuda"), lr=float("nan"))
+
+
+@pytest.mark.parametrize("n,group", [(256, 128), (1024, 128), (96, 32), (4096, 128)])
+def test_pairwise_train_step_gradients(n, group):
+    """The pairwise ranking loss (groups of consecutive rows, targets the log
+    runtimes): loss and every gradient against the oracle's binary64
+    definition on the same bf16 network."""
+    arch = oracle.arch_cdna4()
+    b = feature_batch(50 + n % 13, [3 * n + 64])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:n]
+    assert f.shape[0] == n
+    p, mean, inv, s = surrogate(9, f)
+    rng = np.random.default_rng(n + group)
+    # measured times loosely following the plain key, with ties
+    y = np.round(f[:, 22] + 0.7 * rng.standard_normal(n), 1).astype(np.float32)
+    say("pairwise step n", n, "group", group)
+    loss = float(s.train_step(torch.from_numpy(f).cuda(), torch.from_numpy(y).cuda(), lr=1e-3, group=group).item())
+    torch.cuda.synchronize()
+    x = mlp.normalise(f, mean, inv)
+    ref_loss, ref_g, _ = mlp.ranking_loss_and_grads(p, x, f[:, 22].astype(np.float64), y, group)
+    assert abs(loss - ref_loss) <= 2 ** -6 * ref_loss, (loss, ref_loss)
+    got = _grads_flat(s.grad.cpu().numpy())
+    for k in NAMES:
+        r = np.asarray(ref_g[k], np.float64).reshape(-1)
+        g = got[k]
+        nr = np.linalg.norm(r)
+        if nr == 0:
+            assert np.all(g == 0), k
+            continue
+        rel = np.linalg.norm(g - r) / nr
+        cos = float(g @ r) / (np.linalg.norm(g) * nr)
+        assert rel <= 2e-2 and cos >= 0.999, (k, rel, cos)
+
+
+def test_pairwise_training_orders_groups():
+    """Training on the ranking loss alone lowers it and raises the rank
+    correlation of z with the measured order."""
+    arch = oracle.arch_cdna4()
+    b = feature_batch(60, [9000])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:4096]
+    p, mean, inv, s = surrogate(13, f)
+    rng = np.random.default_rng(3)
+    # "measured" order: the plain key plus a smooth function of other features
+    y = (f[:, 22] + 1.5 * np.sin(3.0 * f[:, 10]) + 0.01 * rng.standard_normal(f.shape[0])).astype(np.float32)
+    ft, yt = torch.from_numpy(f).cuda(), torch.from_numpy(y).cuda()
+    losses = [float(s.train_step(ft, yt, lr=3e-3, group=128).item()) for _ in range(150)]
+    torch.cuda.synchronize()
+    assert losses[-1] < 0.8 * losses[0], (losses[0], losses[-1])
+    d = torch.empty(f.shape[0], device="cuda")
+    s.forward(ft, out=d)
+    z = f[:, 22] + d.cpu().numpy()
+    rho_plain = np.mean([mlp.spearman(f[i:i + 128, 22], y[i:i + 128]) for i in range(0, 4096, 128)])
+    rho_z = np.mean([mlp.spearman(z[i:i + 128], y[i:i + 128]) for i in range(0, 4096, 128)])
+    say("pairwise training: loss", losses[0], "->", losses[-1], "spearman", rho_plain, "->", rho_z)
+    assert rho_z > rho_plain + 0.05

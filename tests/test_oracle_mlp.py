@@ -102,3 +102,64 @@ def test_quantised_forward_uses_bf16_weights_and_activations():
     assert np.array_equal(fw["h1"], mlp.bf16(fw["h1"]))
     assert np.array_equal(fw["W2"], mlp.bf16(p["W2"]))
     assert fw["delta"].shape == (4,)
+
+
+def test_pairwise_loss_hand_cases():
+    # one ordered pair at equal keys: softplus(0) = ln 2, gradient +-sigma(0)
+    loss, g = mlp.pairwise_loss(np.array([0.0, 0.0]), np.array([1.0, 2.0]), 2)
+    assert abs(loss - np.log(2.0)) < 1e-15 and g.tolist() == [0.5, -0.5]
+    # equal measured times: no pair, no loss
+    loss, g = mlp.pairwise_loss(np.array([0.3, -1.0]), np.array([1.0, 1.0]), 2)
+    assert loss == 0.0 and g.tolist() == [0.0, 0.0]
+    # keys in the measured order with a wide margin cost almost nothing; the
+    # reverse order costs about the margin per pair
+    y = np.arange(4.0)
+    good, _ = mlp.pairwise_loss(np.array([0.0, 40.0, 80.0, 120.0]), y, 4)
+    bad, _ = mlp.pairwise_loss(np.array([120.0, 80.0, 40.0, 0.0]), y, 4)
+    assert good < 1e-15 and abs(bad - 400.0 / 6.0) < 1e-12   # mean of 40, 80, 120, 40, 80, 40
+    # two groups: the mean over groups of each group's pair mean
+    loss, _ = mlp.pairwise_loss(np.array([0.0, 0.0, 5.0, 0.0]), np.array([1.0, 2.0, 1.0, 2.0]), 2)
+    assert abs(loss - 0.5 * (np.log(2.0) + np.log1p(np.exp(5.0)))) < 1e-12
+
+
+def test_pairwise_loss_invariance_and_gradient():
+    g = np.random.default_rng(4)
+    z = g.standard_normal(24)
+    y = g.integers(0, 6, 24).astype(np.float64)       # ties within groups
+    loss, grad = mlp.pairwise_loss(z, y, 8)
+    shifted = z.copy()
+    shifted[8:16] += 3.0                              # a constant within one group changes nothing
+    assert abs(mlp.pairwise_loss(shifted, y, 8)[0] - loss) < 1e-12
+    eps = 1e-6
+    for i in range(z.size):
+        zp, zm = z.copy(), z.copy()
+        zp[i] += eps
+        zm[i] -= eps
+        num = (mlp.pairwise_loss(zp, y, 8)[0] - mlp.pairwise_loss(zm, y, 8)[0]) / (2 * eps)
+        assert abs(num - grad[i]) <= 1e-8 + 1e-6 * abs(grad[i]), i
+    assert abs(grad[:8].sum()) < 1e-12                # each pair moves its two keys in opposite directions
+
+
+def test_ranking_backward_matches_finite_differences():
+    g = np.random.default_rng(1)
+    p = mlp.init_params(seed=5, hidden=8)
+    p = {k: v.astype(np.float64) for k, v in p.items()}
+    p["W1"][:, 24:] = 0.0
+    x = g.standard_normal((16, 32))
+    x[:, 24:] = 0.0
+    ln_s = g.standard_normal(16)
+    y = g.standard_normal(16)
+    loss, grads, _ = mlp.ranking_loss_and_grads(p, x, ln_s, y, 8, quantise=False)
+    eps = 1e-6
+    for name in ("W1", "b2", "w3", "b3"):
+        flat = p[name].reshape(-1)
+        for i in range(0, flat.size, max(1, flat.size // 24)):
+            old = flat[i]
+            flat[i] = old + eps
+            lp = mlp.ranking_loss_and_grads(p, x, ln_s, y, 8, quantise=False)[0]
+            flat[i] = old - eps
+            lm = mlp.ranking_loss_and_grads(p, x, ln_s, y, 8, quantise=False)[0]
+            flat[i] = old
+            num = (lp - lm) / (2 * eps)
+            ana = np.asarray(grads[name]).reshape(-1)[i]
+            assert abs(num - ana) <= 1e-9 + 1e-6 * abs(ana), (name, i, num, ana)
