@@ -238,10 +238,11 @@ def test_pairwise_train_step_gradients(n, group):
     for k in NAMES:
         r = np.asarray(ref_g[k], np.float64).reshape(-1)
         g = got[k]
-        nr = np.linalg.norm(r)
-        if nr == 0:
-            assert np.all(g == 0), k
+        if k == "b3":
+            # every pair moves its two keys oppositely: dL/db3 = sum of dL/dz = 0
+            assert abs(r[0]) < 1e-12 and abs(g[0]) <= 1e-6, (r, g)
             continue
+        nr = np.linalg.norm(r)
         rel = np.linalg.norm(g - r) / nr
         cos = float(g @ r) / (np.linalg.norm(g) * nr)
         assert rel <= 2e-2 and cos >= 0.999, (k, rel, cos)
