@@ -117,8 +117,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: measures one GPU only (the model's batch shards by variant with no "
-              "exchange but the top-k gather; see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: a batch shards by variant, each GPU scoring its own segments "
+              "with no exchange but a gather of the top-k rows; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -108,6 +108,40 @@ def search_regret(key: np.ndarray, t: np.ndarray, k: int):
     return float(t[order].min() / t.min() - 1.0), float(t[order].sum() / t.sum())
 
 
+def anneal_search_regret(key: np.ndarray, t: np.ndarray, k: int, g: np.random.Generator, shape=(16, 8),
+                         temp0: float = 0.3, cooling: float = 0.85, max_steps: int = 400):
+    """Simulated annealing over the configuration grid (block-size index x
+    unroll index, neighbours one step along either axis), started at the
+    key's best configuration and stopped once k distinct configurations have
+    been timed (each timing read from t).  Moves are accepted by the
+    Metropolis rule on log time with a geometric cooling schedule.  Returns
+    the regret of the fastest configuration timed and its timing share."""
+    nT, nU = shape
+    timed = {}
+
+    def time_of(c):
+        if c not in timed:
+            timed[c] = t[c]
+        return timed[c]
+
+    cur = int(np.argmin(key))
+    f_cur = np.log(time_of(cur))
+    temp = temp0
+    for _ in range(max_steps):
+        if len(timed) >= k:
+            break
+        iT, iU = divmod(cur, nU)
+        moves = [(iT + d, iU) for d in (-1, 1) if 0 <= iT + d < nT] + [(iT, iU + d) for d in (-1, 1) if 0 <= iU + d < nU]
+        nT2, nU2 = moves[int(g.integers(len(moves)))]
+        nxt = nT2 * nU + nU2
+        f_nxt = np.log(time_of(nxt))
+        if f_nxt <= f_cur or g.random() < np.exp(-(f_nxt - f_cur) / temp):
+            cur, f_cur = nxt, f_nxt
+        temp *= cooling
+    best = min(timed.values())
+    return float(best / t.min() - 1.0), float(sum(timed.values()) / t.sum())
+
+
 def random_search_regret(t: np.ndarray, k: int, draws: int, g: np.random.Generator):
     """The same budget spent on k configurations drawn at random (without
     replacement): mean regret and mean time share over `draws` draws."""
@@ -208,8 +242,12 @@ def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, 
             p = np.array([search_regret(ln_s[i], ms[i], k) for i in ids])
             c = np.array([search_regret(z[i], ms[i], k) for i in ids])
             rnd = np.array([random_search_regret(ms[i], k, 32, g) for i in ids])
+            sa_c = np.array([anneal_search_regret(z[i], ms[i], k, g) for i in ids])
+            sa_p = np.array([anneal_search_regret(ln_s[i], ms[i], k, g) for i in ids])
             search[str(k)] = {"regret_plain": float(p[:, 0].mean()), "regret_corrected": float(c[:, 0].mean()),
                               "regret_random": float(rnd[:, 0].mean()),
+                              "regret_anneal_plain": float(sa_p[:, 0].mean()),
+                              "regret_anneal_corrected": float(sa_c[:, 0].mean()),
                               "time_share_plain": float(p[:, 1].mean()),
                               "time_share_corrected": float(c[:, 1].mean()),
                               "time_share_random": float(rnd[:, 1].mean())}

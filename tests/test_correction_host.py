@@ -65,3 +65,21 @@ def test_random_search_regret():
     r1, s1 = correction.random_search_regret(t, 1, 20000, g)
     assert abs(r1 - (0 + 1 + 2 + 3) / 4) < 0.05          # mean regret of one random pick
     assert abs(s1 - 0.25) < 0.01
+
+
+def test_anneal_search_regret():
+    g = np.random.default_rng(1)
+    # a bowl over the 16 x 8 grid with its minimum at (9, 5)
+    iT, iU = np.meshgrid(np.arange(16), np.arange(8), indexing="ij")
+    t = (1.0 + 0.05 * ((iT - 9) ** 2 + (iU - 5) ** 2)).reshape(-1)
+    key_at_min = np.zeros(128)
+    key_at_min[9 * 8 + 5] = -1.0
+    r, share = correction.anneal_search_regret(key_at_min, t, 1, g)
+    assert r == 0.0 and abs(share - t.min() / t.sum()) < 1e-15     # started at the optimum, one timing
+    key_far = np.zeros(128)
+    key_far[0] = -1.0
+    r_few = np.mean([correction.anneal_search_regret(key_far, t, 2, g)[0] for _ in range(50)])
+    r_many = np.mean([correction.anneal_search_regret(key_far, t, 40, g)[0] for _ in range(50)])
+    assert r_many < r_few                                           # more timings, closer to the bowl's bottom
+    _, share = correction.anneal_search_regret(key_far, t, 16, g)
+    assert share <= 16 * t.max() / t.sum() + 1e-12                 # never more than k distinct timings
