@@ -24,6 +24,9 @@ Prints ONE JSON line (rank 0):
   product      the same evaluations as a product space scored without rows
                (the 16,384 configurations are the full product of the four
                value sets)
+  stream_ceiling  a pure stream of the same 24 B per evaluation with no model
+               arithmetic (fastest of a sweep of launch shapes): the practical
+               memory ceiling of the plain pass on this device
 """
 from __future__ import annotations
 
@@ -233,9 +236,36 @@ def main():
             line["corrected"] = corrected_leg(arch, var, cfg, n_var, n_evals, sur, args.corrected_steps)
         if args.product_steps > 0:
             line["product"] = product_leg(arch, var, n_var, n_evals, outs, args.product_steps)
+        line["stream_ceiling"] = stream_ceiling(cfg, n_evals, achieved)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def stream_ceiling(cfg, n_evals: int, achieved: float) -> dict:
+    """A pure stream of the plain pass's traffic (the four configuration
+    columns read, two 4-byte columns written, no model arithmetic) over a
+    sweep of launch shapes: the fastest is the practical memory ceiling the
+    plain pass is set against."""
+    import torch
+
+    from paper_1701_08547_amd import api
+
+    cols = [cfg[c] for c in ("block", "unroll", "regs", "grid")]
+    outs = [torch.empty(n_evals, dtype=torch.int32, device=cols[0].device) for _ in range(2)]
+    best = None
+    for nt in (False, True):
+        for items in (1, 2, 4):
+            for bpc in (0, 4, 8, 16, 32):
+                ms = api.rt_stream(cols, outs, items=items, blocks_per_cu=bpc, nontemporal=nt, reps=20)
+                if best is None or ms < best[0]:
+                    best = (ms, items, bpc, nt)
+    torch.cuda.synchronize()
+    gbs = BYTES_PER_EVAL * n_evals / (best[0] * 1e-3) / 1e9
+    return {"GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "ms": best[0],
+            "shape": {"items_per_lane": best[1], "blocks_per_cu": best[2], "nontemporal_stores": best[3]},
+            "plain_vs_stream": achieved / gbs,
+            "kernel": "sa_rt_stream: 16 B read + 8 B written per element, %d elements, mean of 20 back-to-back launches" % n_evals}
 
 
 def product_leg(arch, var, n_var, n_evals, outs, steps: int) -> dict:

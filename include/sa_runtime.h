@@ -86,6 +86,25 @@ int32_t sa_rt_measure(int32_t family, int64_t n, const float *a, const float *b,
 enum { SA_CPI_FP = 0, SA_CPI_INT = 1, SA_CPI_MEM = 2, SA_CPI_CTRL = 3, SA_CPI_SYNC = 4, SA_CPI_REG = 5 };
 int32_t sa_rt_cpi(int32_t category, int32_t reps, float *buf, float *cpi_out, float *ms_out, void *stream);
 
+/* Memory ceiling of a scoring pass (the bytes it must move, Sec. III's
+ * per-configuration evaluation of Eqs. 1-6 reads one configuration row and
+ * writes its results): a stream of n elements of four int32 input columns
+ * c0..c3 and two int32 output columns, o0 = c0 + c1 and o1 = c2 ^ c3 element
+ * by element (wrapping), i.e. 24 bytes per element with no other work.
+ * Columns: device buffers of n int32, 16-byte aligned, caller-owned; n a
+ * positive multiple of 4.  Launch shape: 256-thread workgroups, each lane
+ * moving `items` (1, 2 or 4) 16-byte vectors per column per iteration;
+ * blocks_per_cu = 0 covers the columns in one pass of workgroups,
+ * 1..64 runs that many workgroups per compute unit over a grid-stride loop;
+ * nontemporal = 1 writes the outputs with non-temporal stores (0: ordinary
+ * stores).  One warm-up launch, then `reps` (1..64) launches back to back between two
+ * HIP events on `stream`; ms_out = their mean duration (milliseconds).
+ * Synchronous.  Returns 0, -1 on an invalid argument (nothing launched) or
+ * -5 on a HIP failure; sa_rt_last_error() holds the message. */
+int32_t sa_rt_stream(int64_t n, const int32_t *c0, const int32_t *c1, const int32_t *c2, const int32_t *c3,
+                     int32_t *o0, int32_t *o1, int32_t items, int32_t blocks_per_cu, int32_t nontemporal,
+                     int32_t reps, float *ms_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

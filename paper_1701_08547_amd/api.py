@@ -40,6 +40,7 @@ EXPORTED = (
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step", "sa_surrogate_train_step_pairwise",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure", "sa_rt_cpi",
+    "sa_rt_stream",
     "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
     "sa_product_workspace_bytes", "sa_score_product",
 )
@@ -174,6 +175,8 @@ def lib():
             L.sa_rt_measure.restype = i32
             L.sa_rt_cpi.argtypes = [i32, i32, vp, vp, vp, vp]
             L.sa_rt_cpi.restype = i32
+            L.sa_rt_stream.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]
+            L.sa_rt_stream.restype = i32
             _lib = L
     return _lib
 
@@ -427,6 +430,22 @@ def headroom(arch: dict, block, regs=None, stream=None):
     _check(lib().sa_headroom(ctypes.byref(a), _ptr(block, torch.int32, "block"), _ptr(regs, torch.int32, "regs"), n,
                              _ptr(r_star, torch.int32), _ptr(s_star, torch.int32), _stream(stream)))
     return r_star, s_star
+
+
+def rt_stream(cols, outs, *, items: int = 1, blocks_per_cu: int = 0, nontemporal: bool = False, reps: int = 5,
+              stream=None) -> float:
+    """Median milliseconds of a pure stream of a scoring pass's traffic
+    (sa_rt_stream): four int32 columns read, outs[0] = c0 + c1 and
+    outs[1] = c2 ^ c3 written."""
+    torch = _torch()
+    n = int(cols[0].numel())
+    ms = ctypes.c_float(0.0)
+    st = lib().sa_rt_stream(n, *[_ptr(c, torch.int32, "column") for c in cols],
+                            *[_ptr(o, torch.int32, "output") for o in outs], int(items), int(blocks_per_cu),
+                            int(bool(nontemporal)), int(reps), ctypes.byref(ms), _stream(stream))
+    if st != 0:
+        raise SAError(st, lib().sa_rt_last_error().decode())
+    return float(ms.value)
 
 
 def score_suggested(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: bool = False,

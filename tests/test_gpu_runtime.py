@@ -88,3 +88,21 @@ def test_protocol_order_statistic_and_dataset():
     assert np.median(ms_min[0] / ms[0]) <= 1.0 + 1e-6
     rows = rd.static_rows(inst, n_cu)
     assert rows["n_fp"].size == 3 * rd.N_CFG and np.all(rows["grid"] >= 1)
+
+
+@pytest.mark.parametrize("items,bpc,nt", [(1, 0, 0), (2, 0, 1), (4, 0, 0), (1, 1, 1), (2, 4, 0), (4, 2, 1)])
+def test_stream_ceiling_moves_every_element(items, bpc, nt):
+    """The stream-ceiling kernel writes c0 + c1 (wrapping) and c2 ^ c3 for
+    every element, in one pass of workgroups and over a grid-stride loop,
+    with a ragged last workgroup."""
+    n = 4 * (256 * 4 * 97 + 37)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    cols = [torch.randint(-2**31, 2**31 - 1, (n,), generator=g, device="cuda", dtype=torch.int32) for _ in range(4)]
+    outs = [torch.full((n,), 7, dtype=torch.int32, device="cuda") for _ in range(2)]
+    say("stream", n, items, bpc, nt)
+    ms = api.rt_stream(cols, outs, items=items, blocks_per_cu=bpc, nontemporal=nt, reps=2)
+    torch.cuda.synchronize()
+    assert ms > 0
+    c = [x.cpu().numpy() for x in cols]
+    assert np.array_equal(outs[0].cpu().numpy(), (c[0].astype(np.int64) + c[1]).astype(np.uint32).view(np.int32))
+    assert np.array_equal(outs[1].cpu().numpy(), c[2] ^ c[3])

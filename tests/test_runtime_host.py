@@ -191,6 +191,31 @@ def test_cpi_argument_errors():
     assert b"NULL" in L.sa_rt_last_error()
 
 
+def test_stream_argument_errors():
+    """Invalid stream-ceiling arguments are refused before anything is
+    launched (no GPU needed)."""
+    L = api.lib()
+    p = ctypes.c_void_p(4096)
+    ms = ctypes.c_float(0.0)
+    ok = (p, p, p, p, p, p)
+    assert L.sa_rt_stream(0, *ok, 1, 0, 0, 3, ctypes.byref(ms), None) == -1
+    assert L.sa_rt_stream(6, *ok, 1, 0, 0, 3, ctypes.byref(ms), None) == -1
+    assert b"multiple of 4" in L.sa_rt_last_error()
+    for items in (0, 3, 8):
+        assert L.sa_rt_stream(64, *ok, items, 0, 0, 3, ctypes.byref(ms), None) == -1
+    assert L.sa_rt_stream(64, *ok, 1, -1, 0, 3, ctypes.byref(ms), None) == -1
+    assert L.sa_rt_stream(64, *ok, 1, 65, 0, 3, ctypes.byref(ms), None) == -1
+    assert L.sa_rt_stream(64, *ok, 1, 0, 0, 0, ctypes.byref(ms), None) == -1
+    assert L.sa_rt_stream(64, *ok, 1, 0, 0, 65, ctypes.byref(ms), None) == -1
+    assert L.sa_rt_stream(64, p, p, None, p, p, p, 1, 0, 0, 3, ctypes.byref(ms), None) == -1
+    assert b"NULL" in L.sa_rt_last_error()
+    assert L.sa_rt_stream(64, p, p, p, p, p, ctypes.c_void_p(4100), 1, 0, 0, 3, ctypes.byref(ms), None) == -1
+    assert b"aligned" in L.sa_rt_last_error()
+    assert L.sa_rt_stream(64, *ok, 1, 0, 0, 3, None, None) == -1
+    assert L.sa_rt_stream(64, *ok, 1, 0, 2, 3, ctypes.byref(ms), None) == -1
+    assert b"nontemporal" in L.sa_rt_last_error()
+
+
 def test_calibrated_descriptor_mapping():
     from paper_1701_08547_amd import calibration
 
