@@ -13,7 +13,9 @@ Prints ONE JSON line (rank 0):
   value        configurations scored per second (whole job)
   roofline     the evaluation kernel against MI355X HBM peak (8 TB/s):
                algorithmic bytes = 24 B per evaluation (16 B of configuration
-               columns read, 4 B occupancy + 4 B score written)
+               columns read, 4 B occupancy + 4 B score written); valu_side
+               sets its counted vector instructions against the FP32 vector
+               peak, to show which bound is active
   cpu_baseline the CPU oracle (binary32 mode + top-8) on the host cores, over
                repetitions of the same workload for ~10 s
   regret       top-1 regret of the plain and the corrected ranking against
@@ -42,6 +44,8 @@ sys.path.insert(0, ROOT)
 METRIC = "configs scored/sec, plain vs MLP-corrected; top-1 regret vs measured runtime"
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# 157.3 TFLOP/s FP32 vector peak, a fused multiply-add counting two: lane operations per second
+VALU_PEAK_LANE_OPS = 157.3e12 / 2
 MLP_FLOP_PER_EVAL = 2 * (32 * 128 + 128 * 128 + 128)
 BYTES_PER_EVAL = 24
 K = 8
@@ -58,6 +62,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c1.json"),
                    help="JSON with measured HBM bytes per launch of the evaluation kernel")
+    p.add_argument("--valu", default=os.path.join(ROOT, "profiles", "valu_c1.json"),
+                   help="JSON with counted vector instructions per launch of the evaluation kernel")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 256,000 KiB (counter calibration under rocprofv3)")
     p.add_argument("--corrected-steps", type=int, default=10,
@@ -193,6 +199,15 @@ def main():
             t = json.load(f)
         if t.get("source_digest") == source_digest():
             traffic = t.get("bytes_per_launch")
+    valu_side = None
+    if os.path.exists(args.valu):
+        with open(args.valu) as f:
+            vc = json.load(f)
+        if vc.get("source_digest") == source_digest():
+            lane_ops = vc["valu_wave_insts_per_launch"] * 64 / (mean_ms * 1e-3)
+            valu_side = {"lane_ops_per_s": lane_ops, "peak": VALU_PEAK_LANE_OPS, "frac": lane_ops / VALU_PEAK_LANE_OPS,
+                         "wave_insts_per_eval": vc["valu_wave_insts_per_launch"] / n_evals,
+                         "note": "SQ_INSTS_VALU counted at plan shape (8192,1,4) x 64 lanes / event time per launch"}
 
     line = {
         "metric": METRIC,
@@ -226,6 +241,7 @@ def main():
             "traffic": traffic,
             "kernel": "sa_plan_kernel, one launch per step (HIP events around the K-launch graph replay)",
             "event_ms_mean": mean_ms,
+            "valu_side": valu_side,
         },
     }
     if not args.only_plain:
