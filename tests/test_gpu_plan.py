@@ -162,3 +162,26 @@ def test_plan_c2_sampled():
     assert np.array_equal(ref["val"].view(np.uint32), val[rows].view(np.uint32))
     del var, cfg
     torch.cuda.empty_cache()
+
+
+def test_plan_c1_every_autotuner_shape():
+    """The benchmark workload (1,000 variants x 16,384 configurations, top-8,
+    the device's own descriptor) compared in full with the oracle at each of
+    the 36 shapes the autotuner chooses from and at the one it picks here:
+    whichever launch configuration bench.py ends up timing is covered."""
+    a = api.arch_default(0)
+    b = workloads.c1(n_cu=a["n_cu"])
+    ref = oracle.run(a, b.variants, b.configs(), k=8)
+    var, cfg = api.device_batch(b)
+    picked, _ = api.autotune(a, var, cfg, k=8, reps=2)
+    shapes = [(t, i, w) for t in (1024, 2048, 4096, 8192) for i in (1, 2, 4) for w in (4, 8, 16)]
+    assert tuple(picked) in shapes
+    for shape in shapes + [tuple(picked)]:
+        say("c1 shape", shape)
+        plan = api.Plan(b.seg, k=8, shape=shape)
+        ws = api.Workspace(plan.workspace_bytes, "cuda")
+        o = plan.score(a, var, cfg, workspace=ws)
+        torch.cuda.synchronize()
+        check(ref, {key: t.cpu().numpy() for key, t in o.items()})
+        del o, ws, plan
+    torch.cuda.empty_cache()
