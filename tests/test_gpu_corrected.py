@@ -176,3 +176,62 @@ def test_corrected_plain_outputs_unchanged_without_network():
     ref = oracle.run(arch, b.variants, b.configs(), k=8)
     assert np.array_equal(got["score"].cpu().numpy().view(np.uint32), ref["score32"].view(np.uint32))
     assert np.array_equal(got["idx"].cpu().numpy(), ref["idx"])
+
+
+def test_corrected_c1_full_size_sampled():
+    """The benchmark workload in the launch configuration bench.py times for
+    its corrected leg (1,000 variants x 16,384 configurations, top-8, the
+    device's descriptor, default tile): occupancy equal to the oracle's
+    everywhere, z bit-identical to the unfused composition everywhere, and on
+    40 sampled variants (655,360 evaluations) z within the oracle's band and
+    the top-8 rows valid against the oracle's ranking."""
+    a = api.arch_default(0)
+    b = workloads.c1(n_cu=a["n_cu"])
+    g = np.random.default_rng(170108547)
+    vs = np.sort(g.choice(b.n_var, 40, replace=False))
+    fs = {}
+    for v in vs:
+        lo, hi = int(b.seg[v]), int(b.seg[v + 1])
+        vv = {key: x[v] for key, x in b.variants.items()}
+        fs[v] = oracle.features(a, vv, b.block[lo:hi], b.unroll[lo:hi], b.regs[lo:hi], b.grid[lo:hi])
+    ref = oracle.run(a, b.variants, b.configs(), k=0)
+    legal = np.isfinite(ref["score64"])
+    fl = np.concatenate([fs[v][legal[int(b.seg[v]):int(b.seg[v + 1])]] for v in vs])
+    mean = fl.mean(0).astype(np.float32)
+    sd = fl.std(0)
+    inv = np.where(sd > 0, 1.0 / np.maximum(sd, 1e-12), 1.0).astype(np.float32)
+    p = mlp.init_params(seed=3)
+    p["b3"] = np.array([0.1], np.float32)
+    sur = api.Surrogate(p, mean, inv)
+    var, cfg = api.device_batch(b)
+    say("corrected C1 full size")
+    got = api.score(a, var, cfg, k=8, mlp=sur)
+    torch.cuda.synchronize()
+    occ = got["occ"].cpu().numpy()
+    z = got["score"].cpu().numpy()
+    assert np.array_equal(occ, ref["occ"])
+    feat, delta, z_ref = unfused(a, var, cfg, sur, b.n_evals)
+    zr = np.where(legal, z_ref.cpu().numpy(), np.float32(np.inf))
+    del feat, delta, z_ref
+    assert np.array_equal(z.view(np.uint32), zr.view(np.uint32))
+    idx = got["idx"].cpu().numpy()
+    for v in vs:
+        lo, hi = int(b.seg[v]), int(b.seg[v + 1])
+        lg = legal[lo:hi]
+        d_or = mlp.forward(p, mlp.normalise(fs[v][lg], mean, inv))["delta"]
+        ln_s = np.log(ref["score64"][lo:hi][lg])
+        band = 2.0 ** -7 * (1.0 + np.abs(d_or)) + 2e-5 * (1.0 + np.abs(ln_s))
+        zo = np.full(hi - lo, np.inf)
+        zo[lg] = ln_s + d_or
+        err = np.abs(z[lo:hi][lg].astype(np.float64) - zo[lg])
+        assert np.all(err <= band), (int(v), err.max())
+        n_legal = int(lg.sum())
+        row = idx[v]
+        assert np.all(row[: min(8, n_legal)] >= 0) and np.all(row[min(8, n_legal):] == -1)
+        if n_legal:
+            kth = np.sort(zo)[min(8, n_legal) - 1]
+            sel = row[row >= 0]
+            assert len(set(sel.tolist())) == sel.size
+            assert np.all(zo[sel] <= kth + 2 * band.max())
+    del got, var, cfg
+    torch.cuda.empty_cache()
