@@ -73,6 +73,9 @@ def parse():
     p.add_argument("--product-steps", type=int, default=20,
                    help="timed launches of the same workload as a product space without rows (0: skip)")
     p.add_argument("--only-plain", action="store_true", help="the plain leg alone (profiling runs)")
+    p.add_argument("--oracle-timings", action="store_true",
+                   help="host only: the CPU oracle on the 1-, 1,000- and 10,000-variant batches, one thread and "
+                        "all threads (no GPU work)")
     p.add_argument("--shape", default=None, help="tile,items,waves: fixed plan shape, no autotuning")
     return p.parse_args()
 
@@ -120,10 +123,51 @@ def cpu_baseline(batch, seconds: float) -> dict:
                       "top-%d, %.1f s" % (reps, batch.n_evals, K, dt)}
 
 
+def oracle_timings():
+    """The CPU oracle (binary32 scores + occupancy + top-k, as in the
+    cpu_baseline leg) on the three batch shapes, one thread and all threads:
+    the best of a few repetitions, each repetition a full pass."""
+    import platform
+
+    import oracle
+    from paper_1701_08547_amd import workloads
+
+    arch = oracle.arch_cdna4()
+    nt = oracle.max_threads()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    out = {"host": {"cpu": model or platform.processor(), "threads": nt, "cpus": os.cpu_count()}, "batches": []}
+    for name, batch, k in (("1 x 4,096 (T x U x R), top-8", workloads.c0(), 8),
+                           ("1,000 x 16,384, top-8", workloads.c1(), 8),
+                           ("10,000 variants, spaces log-uniform in [64, 262,144], top-16", workloads.c2(), 16)):
+        cfgs = batch.configs()
+        row = {"workload": name, "evaluations": batch.n_evals}
+        for threads in (1, nt):
+            best, reps, t_all = None, 0, time.perf_counter()
+            while reps < 3 and (reps == 0 or time.perf_counter() - t_all < 20.0):
+                t0 = time.perf_counter()
+                oracle.run(arch, batch.variants, cfgs, k=k, want_occ=True, want_f32=True, want_f64=False,
+                           nthreads=threads)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+                reps += 1
+            row["threads_%d" % threads] = {"seconds": best, "configs_per_s": batch.n_evals / best, "passes": reps}
+        out["batches"].append(row)
+        print(json.dumps(row), flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.oracle_timings:
+        oracle_timings()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: a batch shards by variant, each GPU scoring its own segments "
