@@ -129,6 +129,8 @@ def oracle_timings():
     the best of a few repetitions, each repetition a full pass."""
     import platform
 
+    import numpy as np
+
     import oracle
     from paper_1701_08547_amd import workloads
 
@@ -158,6 +160,22 @@ def oracle_timings():
             row["threads_%d" % threads] = {"seconds": best, "configs_per_s": batch.n_evals / best, "passes": reps}
         out["batches"].append(row)
         print(json.dumps(row), flush=True)
+    # the 100,000-variant streamed batch: a seeded sample of 200 variants, rows rebuilt on the host (not
+    # timed), extrapolated to the whole batch by evaluation count
+    c4 = workloads.c4()
+    vids = np.sort(np.random.default_rng(170108547).choice(c4.n_var, 200, replace=False))
+    sub = c4.subset(vids)
+    row = {"workload": "100,000 variants, spaces log-uniform in [256, 1,048,576], top-16: sample of 200 variants, "
+                       "extrapolated", "evaluations": c4.n_evals, "sample_evaluations": sub.n_evals}
+    cfgs = sub.configs()
+    for threads in (1, nt):
+        t0 = time.perf_counter()
+        oracle.run(arch, sub.variants, cfgs, k=16, want_occ=True, want_f32=True, want_f64=False, nthreads=threads)
+        dt = time.perf_counter() - t0
+        row["threads_%d" % threads] = {"sample_seconds": dt, "configs_per_s": sub.n_evals / dt,
+                                       "extrapolated_seconds": dt * c4.n_evals / sub.n_evals}
+    out["batches"].append(row)
+    print(json.dumps(row), flush=True)
     print(json.dumps(out), flush=True)
 
 
