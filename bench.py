@@ -73,9 +73,9 @@ def parse():
     p.add_argument("--product-steps", type=int, default=20,
                    help="timed launches of the same workload as a product space without rows (0: skip)")
     p.add_argument("--only-plain", action="store_true", help="the plain leg alone (profiling runs)")
-    p.add_argument("--oracle-timings", action="store_true",
-                   help="host only: the CPU oracle on the 1-, 1,000- and 10,000-variant batches, one thread and "
-                        "all threads (no GPU work)")
+    p.add_argument("--cpu-baseline-batches", action="store_true",
+                   help="host only: the cpu_baseline leg (the CPU oracle) on every batch shape, one thread and all "
+                        "threads (no GPU work)")
     p.add_argument("--shape", default=None, help="tile,items,waves: fixed plan shape, no autotuning")
     return p.parse_args()
 
@@ -123,10 +123,11 @@ def cpu_baseline(batch, seconds: float) -> dict:
                       "top-%d, %.1f s" % (reps, batch.n_evals, K, dt)}
 
 
-def oracle_timings():
-    """The CPU oracle (binary32 scores + occupancy + top-k, as in the
-    cpu_baseline leg) on the three batch shapes, one thread and all threads:
-    the best of a few repetitions, each repetition a full pass."""
+def cpu_baseline_batches():
+    """The cpu_baseline leg on every batch shape: the CPU oracle (binary32
+    scores + occupancy + top-k) with one thread and with all, the best of a
+    few repetitions, each a full pass; the streamed batch on a sample,
+    extrapolated."""
     import platform
 
     import numpy as np
@@ -184,8 +185,8 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.oracle_timings:
-        oracle_timings()
+    if args.cpu_baseline_batches:
+        cpu_baseline_batches()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: a batch shards by variant, each GPU scoring its own segments "
