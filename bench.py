@@ -302,6 +302,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE per launch, counted at plan shape (8192,1,4), scaled by a "
+                            "plain copy; null once the kernel sources differ from the counted ones",
             "kernel": "sa_plan_kernel, one launch per step (HIP events around the K-launch graph replay)",
             "event_ms_mean": mean_ms,
             "valu_side": valu_side,
