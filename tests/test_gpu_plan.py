@@ -185,3 +185,13 @@ def test_plan_c1_every_autotuner_shape():
         check(ref, {key: t.cpu().numpy() for key, t in o.items()})
         del o, ws, plan
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("k,shape", [(1, (1024, 1, 4)), (33, (2048, 2, 8)), (64, (1024, 4, 16)), (64, (8192, 1, 4))])
+def test_plan_k_extremes(k, shape):
+    """k from 1 to the maximum on ragged segments (empty ones, and ones split
+    over several workgroup items): with 16 waves and k = 64 a workgroup's
+    merge runs 1,024 keys through the selection buffer."""
+    b = workloads.custom_batch(90 + k, SIZES, with_grid=True, name="plan-k")
+    ref = oracle.run(oracle.arch_cdna4(), b.variants, b.configs(), k=k)
+    check(ref, run_plan(b, k, shape))
