@@ -152,3 +152,20 @@ def test_product_empty_and_limits():
                                            np.zeros(0, np.int32), None, "p"))[0]
     with pytest.raises(api.SAError):
         api.score_product(arch, var, {"block": list(range(1, 66)), "unroll": [1], "regs": [0]}, k=8)
+
+
+@pytest.mark.parametrize("gpu", ["fermi", "kepler", "maxwell", "pascal"])
+def test_product_paper_descriptors(gpu):
+    """The paper's own GPUs (32-lane warps, their register files, shared
+    memory and block limits): the product pass equals the materialised pass
+    and the oracle."""
+    arch = oracle.arch_paper(gpu)
+    v = workloads.variant_features(11, 910)
+    space = {"block": [32, 64, 96, 128, 192, 256, 512, 1024, 2048], "unroll": [1, 2, 4, 8],
+             "regs": [0, 16, 24, 32, 63, 64, 128, 255, 256], "grid": [13, 26, 100, 1000]}
+    b, ref, got = run_both(arch, v, space, 8)
+    assert_same(ref, got)
+    o = oracle.run(arch, b.variants, b.configs(), k=8, want_f64=False)
+    assert np.array_equal(o["occ"], got["occ"].cpu().numpy())
+    assert np.array_equal(o["score32"].view(np.uint32), got["score"].cpu().numpy().view(np.uint32))
+    assert np.array_equal(o["idx"], got["idx"].cpu().numpy())
