@@ -190,14 +190,15 @@ def train(feat, target, mean, inv_std, epochs: int = 40, batch: int = 4096, lr: 
             perm = (g_perm[:, None] * group + torch.arange(group, device=device)[None, :]).reshape(-1)
         else:
             perm = torch.randperm(n, generator=gen, device=device)
+        # one gather per epoch; each batch is then a contiguous slice of it
+        feat_p = feat.index_select(0, perm)
+        target_p = target.index_select(0, perm)
         tot = torch.zeros((), dtype=torch.float32, device=device)
         nb = 0
         for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
-            idx = perm[b0:b0 + batch]
-            fb = feat.index_select(0, idx).contiguous()
-            tb = target.index_select(0, idx).contiguous()
-            tot += sur.train_step(fb, tb, lr=lr, group=group)
+            tot += sur.train_step(feat_p[b0:b0 + batch], target_p[b0:b0 + batch], lr=lr, group=group)
             nb += 1
+        del feat_p, target_p
         losses.append(float(tot.item()) / max(1, nb))
         if log:
             log("epoch %d loss %.5f" % (ep + 1, losses[-1]))
