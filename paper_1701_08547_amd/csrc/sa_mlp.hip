@@ -286,16 +286,17 @@ __global__ __launch_bounds__(64 * kFwdWaves) void sa_mlp_fwd_kernel(MlpDev M, co
 
 // Forward over the batch with every activation stashed, the loss terms and
 // dL/dDelta = 2 (Delta - r) / n.
-__global__ __launch_bounds__(kMlpThreads) void sa_train_fwd_kernel(MlpDev M, const float *feat, const float *target,
-                                                                    int64_t n, TrainBufs T) {
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void sa_train_fwd_kernel(MlpDev M, const float *feat, const float *target,
+                                                                  int64_t n, TrainBufs T) {
   __shared__ MlpLds s;
-  __shared__ WaveBufs wbuf[kMlpWaves];
+  __shared__ WaveBufs wbuf[WAVES];
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-  load_weights(M, s, tid, kMlpThreads);
+  load_weights(M, s, tid, 64 * WAVES);
   __syncthreads();
   WaveBufs &wb = wbuf[w];
   const int64_t n_blocks = (n + kRows - 1) / kRows;
-  for (int64_t blk = (int64_t)blockIdx.x * kMlpWaves + w; blk < n_blocks; blk += (int64_t)gridDim.x * kMlpWaves) {
+  for (int64_t blk = (int64_t)blockIdx.x * WAVES + w; blk < n_blocks; blk += (int64_t)gridDim.x * WAVES) {
     const int64_t row = blk * kRows + lane;
     float f[kF];
 #pragma unroll
@@ -372,21 +373,22 @@ __global__ __launch_bounds__(256) void sa_train_rank_kernel(const float *feat, c
 
 // Per row: dA2 = (dDelta w3) * GELU'(a2), dH1 = dA2 W2 (MFMA), dA1 = dH1 *
 // GELU'(a1); dA2, dA1 stored bf16 for the weight-gradient contractions.
-__global__ __launch_bounds__(kMlpThreads) void sa_train_bwd_rows_kernel(MlpDev M, int64_t n, TrainBufs T) {
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void sa_train_bwd_rows_kernel(MlpDev M, int64_t n, TrainBufs T) {
   __shared__ uint16_t W2t[kH * kLdH];  // W2 transposed: W2t[k][n] = W2[n][k]
   __shared__ float w3[kH];
-  __shared__ uint16_t G2[kMlpWaves][kRows * kLdH];
+  __shared__ uint16_t G2[WAVES][kRows * kLdH];
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-  for (int i = tid; i < kH * kH; i += kMlpThreads) {
+  for (int i = tid; i < kH * kH; i += 64 * WAVES) {
     const int nn = i / kH, kk = i % kH;
     W2t[kk * kLdH + nn] = M.W2[i];
   }
-  for (int i = tid; i < kH; i += kMlpThreads) w3[i] = bf2f(M.w3[i]);
+  for (int i = tid; i < kH; i += 64 * WAVES) w3[i] = bf2f(M.w3[i]);
   __syncthreads();
   uint16_t *g2 = G2[w];
   const int r = lane & 15, q = lane >> 4;
   const int64_t n_blocks = (n + kRows - 1) / kRows;
-  for (int64_t blk = (int64_t)blockIdx.x * kMlpWaves + w; blk < n_blocks; blk += (int64_t)gridDim.x * kMlpWaves) {
+  for (int64_t blk = (int64_t)blockIdx.x * WAVES + w; blk < n_blocks; blk += (int64_t)gridDim.x * WAVES) {
     const int64_t row = blk * kRows + lane;
     const float gd = row < n ? T.gdelta[row] : 0.0f;
     for (int c = 0; c < kH; ++c) {
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(kMlpThreads) void sa_train_bwd_rows_kernel(MlpDev M
 // Weight gradients, one workgroup per slab of kSlab rows: the slab's
 // contributions to dW2 = dA2^T H1, dW1 = dA1^T X (MFMA over the rows) and to
 // the bias / output-layer sums, written as fp32 partials part[slab][...].
-constexpr int kSlab = 256;
+constexpr int kSlab = 64;  // one 64-row chunk per workgroup: a 4,096-row step spreads over 64 workgroups
 constexpr int kLdT = 64 + 4;  // transposed 64-row chunk, padded
 
 __global__ __launch_bounds__(kMlpThreads) void sa_train_wgrad_kernel(int64_t n, TrainBufs T) {
@@ -560,10 +562,18 @@ int64_t train_slabs(int64_t n) { return (n + kSlab - 1) / kSlab; }
 hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,
                              TrainBufs T, AdamArgs h, float *grad_out, int32_t group, hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  // Batches of up to 1,024 row blocks run one wave per workgroup, so that
+  // their few row blocks spread over as many compute units; larger ones
+  // share each workgroup's staged weights among four waves.
   const int64_t n_blocks = (n + kRows - 1) / kRows;
-  int64_t grid = (n_blocks + kMlpWaves - 1) / kMlpWaves;
+  const bool narrow = n_blocks <= 1024;
+  int64_t grid = narrow ? n_blocks : (n_blocks + kMlpWaves - 1) / kMlpWaves;
   if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(sa_train_fwd_kernel, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, feat, target, n, T);
+  if (narrow)
+    hipLaunchKernelGGL(sa_train_fwd_kernel<1>, dim3((uint32_t)grid), dim3(64), 0, stream, M, feat, target, n, T);
+  else
+    hipLaunchKernelGGL(sa_train_fwd_kernel<kMlpWaves>, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, feat,
+                       target, n, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (group > 0) {
@@ -572,7 +582,11 @@ hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, c
                        stream, feat, target, group, 1.0f / (float)groups, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(sa_train_bwd_rows_kernel, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, n, T);
+  if (narrow)
+    hipLaunchKernelGGL(sa_train_bwd_rows_kernel<1>, dim3((uint32_t)grid), dim3(64), 0, stream, M, n, T);
+  else
+    hipLaunchKernelGGL(sa_train_bwd_rows_kernel<kMlpWaves>, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, n,
+                       T);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t slabs = train_slabs(n);
   hipLaunchKernelGGL(sa_train_wgrad_kernel, dim3((uint32_t)slabs), dim3(kMlpThreads), 0, stream, n, T);
