@@ -317,11 +317,35 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     return sur, rep
 
 
+def time_synthetic(n: int, epochs: int, batch: int, lr: float, seed: int) -> int:
+    """Training throughput alone: n random rows (standard normal features,
+    targets of standard deviation 0.3), one untimed epoch, then `epochs`
+    timed ones."""
+    import time
+
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(170108547 + seed)
+    feat = torch.randn(n, api.N_FEAT, generator=g, device="cuda")
+    target = torch.randn(n, generator=g, device="cuda") * 0.3
+    mean, inv = np.zeros(api.N_FEAT, np.float32), np.ones(api.N_FEAT, np.float32)
+    train(feat, target, mean, inv, epochs=1, batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = train(feat, target, mean, inv, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"rows": n, "epochs": epochs, "batch": batch, "seconds": dt, "ms_per_epoch": dt * 1e3 / epochs,
+                      "loss_last": losses[-1]}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     src = ap.add_mutually_exclusive_group(required=True)
     src.add_argument("--data", help="npz of dataset rows")
     src.add_argument("--parts", nargs="+", help="timing parts of one sampling, assembled here")
+    src.add_argument("--synthetic-rows", type=int, help="time training alone on this many random rows (no report)")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -331,6 +355,8 @@ def main(argv=None):
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
+    if a.synthetic_rows:
+        return time_synthetic(a.synthetic_rows, a.epochs, a.batch, a.lr, a.seed)
     data = load(a.data) if a.data else runtime_dataset.assemble(a.parts)
     sur, rep = run(data, a.epochs, a.batch, a.lr, a.seed, log=log, loss=a.loss)
     if a.out:
