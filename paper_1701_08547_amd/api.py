@@ -281,10 +281,49 @@ def _configs_struct(c: dict) -> SaConfigs:
     return s
 
 
+def _numel(t, n: int, name: str):
+    """Raise unless tensor `t` (None allowed) holds exactly `n` elements: a
+    mis-sized buffer would be read or written out of bounds on the device."""
+    if t is not None and int(t.numel()) != int(n):
+        raise ValueError("%s holds %d elements, expected %d" % (name, int(t.numel()), int(n)))
+
+
+def _variant_sizes(variants: dict) -> int:
+    """Number of variants, every per-variant column checked against it."""
+    t = variants.get("n_fp")
+    if t is None:
+        raise ValueError("variant column n_fp missing")
+    n_var = int(t.numel())
+    for f in VARIANT_COLUMNS:
+        _numel(variants.get(f if f in variants else ("lds" if f == "lds_bytes" else f)), n_var, "variant column " + f)
+    return n_var
+
+
 def _sizes(variants: dict, configs: dict):
+    """(n_var, n_evals) of a batch, with every column's length checked: the
+    per-variant columns against n_var = seg.numel() - 1 and the configuration
+    columns against n_evals = block.numel().  seg's contents (monotone, last
+    entry n_evals) are a documented precondition of the C ABI: checking them
+    would read device memory."""
+    for f in ("seg", "block"):
+        if configs.get(f) is None:
+            raise ValueError("configuration column %s missing" % f)
     n_var = int(configs["seg"].numel()) - 1
+    if n_var < 0:
+        raise ValueError("seg must hold n_var + 1 >= 1 offsets")
     n_evals = int(configs["block"].numel())
+    if _variant_sizes(variants) != n_var:
+        raise ValueError("variant columns hold %d variants, seg describes %d" % (_variant_sizes(variants), n_var))
+    for f in ("unroll", "regs", "grid"):
+        _numel(configs.get(f), n_evals, "configuration column " + f)
     return n_var, n_evals
+
+
+def _check_outputs(o: dict, n_evals: int, n_var: int, k: int):
+    _numel(o.get("occ"), n_evals, "occ")
+    _numel(o.get("score"), n_evals, "score")
+    _numel(o.get("idx"), n_var * k, "idx")
+    _numel(o.get("val"), n_var * k, "val")
 
 
 def occupancy(arch: dict, variants: dict, configs: dict, out=None, stream=None):
@@ -293,6 +332,7 @@ def occupancy(arch: dict, variants: dict, configs: dict, out=None, stream=None):
     n_var, n_evals = _sizes(variants, configs)
     if out is None:
         out = torch.empty(n_evals, dtype=torch.int32, device=configs["block"].device)
+    _numel(out, n_evals, "out")
     a = _arch_struct(arch)
     _check(lib().sa_occupancy(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
                               ctypes.byref(_configs_struct(configs)), n_var, n_evals,
@@ -340,6 +380,8 @@ def score(arch: dict, variants: dict, configs: dict, k: int = 8, *, want_score: 
             workspace = Workspace(workspace_bytes(n_var, n_evals, k), dev)
     for key in ("occ", "score", "idx", "val"):
         o.setdefault(key, None)
+    _check_outputs({key: o[key] for key, want in (("occ", want_occ), ("score", want_score), ("idx", want_topk),
+                                                 ("val", want_topk)) if want}, n_evals, n_var, k)
     a = _arch_struct(arch)
     ws_ptr = workspace.ptr if (want_topk and workspace is not None) else None
     ws_bytes = workspace.nbytes if (want_topk and workspace is not None) else 0
@@ -357,9 +399,10 @@ def suggest(arch: dict, variants: dict, out=None, stream=None):
     """The paper's reduced search space per variant (sa_suggest): int64
     tensor whose bit j keeps the block size wave_size * (j + 1)."""
     torch = _torch()
-    n_var = int(variants["n_fp"].shape[0])
+    n_var = _variant_sizes(variants)
     if out is None:
         out = torch.zeros(n_var, dtype=torch.int64, device=variants["n_fp"].device)
+    _numel(out, n_var, "kept")
     a = _arch_struct(arch)
     _check(lib().sa_suggest(ctypes.byref(a), ctypes.byref(_variants_struct(variants)), n_var,
                             _ptr(out, torch.int64, "kept"), _stream(stream)))
@@ -386,7 +429,7 @@ def score_product(arch: dict, variants: dict, space: dict, k: int = 8, *, want_s
     shared by every variant, without configuration rows (sa_score_product).
     Per-evaluation outputs are indexed v * S + i."""
     torch = _torch()
-    n_var = int(variants["n_fp"].shape[0])
+    n_var = _variant_sizes(variants)
     dev = variants["n_fp"].device
     S = product_size(space)
     n = n_var * S
@@ -407,6 +450,8 @@ def score_product(arch: dict, variants: dict, space: dict, k: int = 8, *, want_s
         workspace = Workspace(int(lib().sa_product_workspace_bytes(n_var, S, int(k))), dev)
     for key in ("occ", "score", "idx", "val"):
         o.setdefault(key, None)
+    _check_outputs({key: o[key] for key, want in (("occ", want_occ), ("score", want_score), ("idx", want_topk),
+                                                 ("val", want_topk)) if want}, n, n_var, k)
     a = _arch_struct(arch)
     _check(lib().sa_score_product(ctypes.byref(a), ctypes.byref(_variants_struct(variants)), n_var, ctypes.byref(ps),
                                   _ptr(o["score"] if want_score else None, torch.float32, "score"),
@@ -423,7 +468,8 @@ def headroom(arch: dict, block, regs=None, stream=None):
     full occupancy for each row's block size (sa_headroom): two int32
     tensors."""
     torch = _torch()
-    n = int(block.shape[0])
+    n = int(block.numel())
+    _numel(regs, n, "regs")
     r_star = torch.empty(n, dtype=torch.int32, device=block.device)
     s_star = torch.empty(n, dtype=torch.int32, device=block.device)
     a = _arch_struct(arch)
@@ -439,6 +485,10 @@ def rt_stream(cols, outs, *, items: int = 1, blocks_per_cu: int = 0, nontemporal
     outs[1] = c2 ^ c3 written."""
     torch = _torch()
     n = int(cols[0].numel())
+    if len(cols) != 4 or len(outs) != 2:
+        raise ValueError("rt_stream takes four columns and two outputs")
+    for i, t in enumerate(list(cols) + list(outs)):
+        _numel(t, n, "stream buffer %d" % i)
     ms = ctypes.c_float(0.0)
     st = lib().sa_rt_stream(n, *[_ptr(c, torch.int32, "column") for c in cols],
                             *[_ptr(o, torch.int32, "output") for o in outs], int(items), int(blocks_per_cu),
@@ -460,6 +510,7 @@ def score_suggested(arch: dict, variants: dict, configs: dict, k: int = 8, *, wa
          "val": torch.empty((n_var, k), dtype=torch.float32, device=dev)}
     if workspace is None:
         workspace = Workspace(workspace_bytes(n_var, n_evals, k), dev)
+    _check_outputs(o, n_evals, n_var, k)
     a = _arch_struct(arch)
     _check(lib().sa_score_suggested(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
                                     ctypes.byref(_configs_struct(configs)), n_var, n_evals,
@@ -569,6 +620,9 @@ class Plan:
               outputs: dict | None = None, workspace: Workspace | None = None, stream=None) -> dict:
         torch = _torch()
         dev = configs["seg"].device
+        if _sizes(variants, configs) != (self.n_var, self.n_evals):
+            raise ValueError("batch of %d variants / %d evaluations, plan made for %d / %d"
+                             % (*_sizes(variants, configs), self.n_var, self.n_evals))
         o = dict(outputs or {})
         if want_occ and o.get("occ") is None:
             o["occ"] = torch.empty(self.n_evals, dtype=torch.int32, device=dev)
@@ -583,6 +637,8 @@ class Plan:
             workspace = Workspace(self.workspace_bytes, dev)
         for key in ("occ", "score", "idx", "val"):
             o.setdefault(key, None)
+        _check_outputs({key: o[key] for key, want in (("occ", want_occ), ("score", want_score), ("idx", want_topk),
+                                                     ("val", want_topk)) if want}, self.n_evals, self.n_var, self.k)
         a = _arch_struct(arch)
         _check(lib().sa_plan_score(self._h, ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
                                    ctypes.byref(_configs_struct(configs)),
@@ -595,6 +651,8 @@ class Plan:
 
     def topk(self, keys, seg, *, workspace: Workspace | None = None, stream=None):
         torch = _torch()
+        _numel(keys, self.n_evals, "keys")
+        _numel(seg, self.n_var + 1, "seg")
         idx = torch.empty((self.n_var, self.k), dtype=torch.int32, device=seg.device)
         val = torch.empty((self.n_var, self.k), dtype=torch.float32, device=seg.device)
         if workspace is None:
@@ -623,6 +681,9 @@ def autotune(arch: dict, variants: dict, configs: dict, k: int = 8, reps: int = 
     o.setdefault("score", None)
     o.setdefault("idx", torch.empty((n_var, k), dtype=torch.int32, device=dev))
     o.setdefault("val", torch.empty((n_var, k), dtype=torch.float32, device=dev))
+    if _sizes(variants, configs) != (n_var, n_evals):
+        raise ValueError("configuration columns do not match seg")
+    _check_outputs(o, n_evals, n_var, k)
     ws = Workspace(int(lib().sa_plan_autotune_workspace_bytes(n_var, n_evals, k)), dev)
     best = SaPlanShape()
     ms = ctypes.c_float()
@@ -651,11 +712,19 @@ def features(arch: dict, variants: dict, configs: dict, out=None, stream=None):
     n_var, n_evals = _sizes(variants, configs)
     if out is None:
         out = torch.empty((n_evals, N_FEAT), dtype=torch.float32, device=configs["seg"].device)
+    _numel(out, n_evals * N_FEAT, "out")
     a = _arch_struct(arch)
     _check(lib().sa_features(ctypes.byref(a), ctypes.byref(_variants_struct(variants)),
                              ctypes.byref(_configs_struct(configs)), n_var, n_evals, _ptr(out, torch.float32, "out"),
                              _stream(stream)))
     return out
+
+
+def _feature_rows(feat) -> int:
+    """Rows of a feature matrix, which must be (n, 24)."""
+    if feat.dim() != 2 or int(feat.shape[1]) != N_FEAT:
+        raise ValueError("features must have shape (n, %d), got %s" % (N_FEAT, tuple(feat.shape)))
+    return int(feat.shape[0])
 
 
 def flat_from_params(p: dict):
@@ -720,9 +789,10 @@ class Surrogate:
 
     def forward(self, feat, out=None, stream=None):
         torch = _torch()
-        n = int(feat.shape[0])
+        n = _feature_rows(feat)
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=feat.device)
+        _numel(out, n, "out")
         m = self.struct()
         _check(lib().sa_surrogate_fwd(ctypes.byref(m), _ptr(feat, torch.float32, "feat"), n,
                                       _ptr(out, torch.float32, "out"), _stream(stream)))
@@ -735,7 +805,8 @@ class Surrogate:
         rows with `target` the measured log runtime
         (sa_surrogate_train_step_pairwise)."""
         torch = _torch()
-        n = int(feat.shape[0])
+        n = _feature_rows(feat)
+        _numel(target, n, "target")
         need = int(lib().sa_surrogate_train_workspace_bytes(n))
         if need and (self._ws is None or self._ws.nbytes < need):
             self._ws = Workspace(need, self.device)
