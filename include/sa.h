@@ -233,9 +233,14 @@ sa_status sa_occupancy(const sa_arch *arch, const sa_variants *variants, const s
  *             order; -1 past the number of legal configurations.
  *   topk_val  float[n_variants * k] or NULL: the matching scores (+inf pad).
  *   k         1 .. 64 when topk_idx or topk_val is given, else ignored.
- *   mlp       NULL for the plain model; not yet accepted here (returns
- *             SA_ERR_UNSUPPORTED): the corrected key is available through
- *             sa_features + sa_surrogate_fwd.
+ *   mlp       NULL for the plain model.  Non-NULL selects the fused
+ *             corrected pass (the learned correction applied inside the
+ *             scoring kernel): score[e] receives the corrected key
+ *             z = ln(score) + Delta (Delta = the network of sa_surrogate_fwd
+ *             on the 24 features of sa_features, +inf when illegal) and the
+ *             top-k ranks by z with the same tie rule.  Its weight pointers
+ *             must be 16-byte aligned (SA_ERR_ALIGN otherwise); every one of
+ *             them is required.
  *   workspace device buffer of sa_workspace_bytes(...) bytes (may be NULL
  *             when no top-k is asked for).  Contents need no initialisation.
  *             Segments that span several wave-tiles leave per-tile partial
@@ -385,11 +390,13 @@ sa_status sa_set_tile(int32_t evals_per_wave);
  * load: 4-, 8- or 16-byte accesses); waves_per_block 4, 8 or 16.
  *
  * sa_plan_create validates the offsets (seg[0] = 0, non-decreasing,
- * seg[n_variants] = n_evals), allocates the plan's device buffer and copies
- * it synchronously: it is a set-up call, not for graph capture.
- * sa_plan_score / sa_plan_topk are asynchronous, allocation-free and
- * capturable, like sa_score / sa_topk; `seg` passed to them must hold the
- * same offsets on the device.
+ * seg[n_variants] = n_evals) and decomposes them on the host; it makes no HIP
+ * call.  The decomposition reaches the device through sa_plan_bind, which
+ * copies it into a caller-owned table of sa_plan_device_bytes(plan) bytes
+ * (the library allocates no device memory).  sa_plan_score / sa_plan_topk are
+ * asynchronous, allocation-free and capturable, like sa_score / sa_topk; they
+ * return SA_ERR_ARG for a plan that was never bound, and `seg` passed to them
+ * must hold the same offsets on the device.
  */
 typedef struct sa_plan sa_plan;
 typedef struct sa_plan_shape {
@@ -400,7 +407,20 @@ typedef struct sa_plan_shape {
 
 sa_status sa_plan_create(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k,
                          const sa_plan_shape *shape /* NULL = 4096, 4, 4 */, sa_plan **out);
+/* Frees the host object only (never the bound table, which the caller owns). */
 sa_status sa_plan_destroy(sa_plan *plan);
+/* Bytes of the device table of a plan (0 for a NULL plan); a multiple of 256. */
+size_t sa_plan_device_bytes(const sa_plan *plan);
+/* Copies the plan's decomposition into `table` (device memory, 256-byte
+ * aligned, at least sa_plan_device_bytes(plan) bytes, caller-owned) with
+ * hipMemcpyAsync on `stream`, and records `table` and the current device's
+ * compute-unit count in the plan.  The copy reads the plan's host memory when
+ * `stream` reaches it: keep the plan alive until then, and keep `table`
+ * alive and unmodified while launches of the plan are pending.  Rebinding
+ * to another table is allowed.  A set-up call: not for graph capture (the
+ * copy's source is pageable host memory).  SA_ERR_ARG (NULL), SA_ERR_ALIGN,
+ * SA_ERR_WORKSPACE (too small), SA_ERR_HIP. */
+sa_status sa_plan_bind(sa_plan *plan, void *table, size_t table_bytes, void *stream);
 /* The plan's decomposition computed on the host only (no device needed):
  * counts, and when the arrays are non-NULL, items (n_items x {kind, slot,
  * v}), waves (n_items x waves_per_block x {e0, e1, v0, v1}) and splits
@@ -424,10 +444,13 @@ sa_status sa_plan_topk(const sa_plan *plan, const float *keys, const int64_t *se
  * {1024, 2048, 4096, 8192} x {1, 2, 4} x {4, 8, 16} on the caller's buffers
  * (outputs are overwritten), `reps` timed runs each after one warm-up, on
  * `stream`, and returns the fastest shape and its median milliseconds.
- * Synchronises; creates and destroys plans.  The workspace must hold
- * sa_plan_autotune_workspace_bytes(...) bytes.
+ * Synchronises; creates, binds and destroys plans (host objects) inside.
+ * The workspace (256-byte aligned) must hold
+ * sa_plan_autotune_workspace_bytes(...) bytes: the largest fragment area of
+ * the candidate shapes followed by their largest device table (0 when the
+ * offsets are invalid).
  */
-size_t sa_plan_autotune_workspace_bytes(int64_t n_variants, int64_t n_evals, int32_t k);
+size_t sa_plan_autotune_workspace_bytes(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k);
 sa_status sa_plan_autotune(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k,
                            const sa_arch *arch, const sa_variants *variants, const sa_configs *configs, float *score,
                            int32_t *occ_waves, int32_t *topk_idx, float *topk_val, void *workspace,

@@ -105,6 +105,28 @@ int32_t sa_rt_stream(int64_t n, const int32_t *c0, const int32_t *c1, const int3
                      int32_t *o0, int32_t *o1, int32_t items, int32_t blocks_per_cu, int32_t nontemporal,
                      int32_t reps, float *ms_out, void *stream);
 
+/* Residency probe for the device limits behind the occupancy bound (Sec.
+ * III-A, Eqs. 1-5; the per-multiprocessor limits of Table I): launches
+ * n_blocks workgroups of `block` threads of a probe kernel that owns exactly
+ * `vgprs` unified registers per lane (the code object declares that count)
+ * with `lds_bytes` of dynamic LDS; each workgroup spins for spin_us
+ * microseconds of real time and writes records[4 b .. 4 b + 3] = {start,
+ * end (device real-time counter ticks), HW_ID, XCC_ID hardware registers of
+ * its first wave}.  The number of workgroups one compute unit holds at once
+ * is the largest number of overlapping [start, end) intervals among the
+ * records of that unit.  api_blocks_per_cu (nullable) receives HIP's own
+ * answer, hipOccupancyMaxActiveBlocksPerMultiprocessor, for the same
+ * kernel, block size and LDS.  Supported (block rounded up to a multiple of
+ * 64, vgprs): (64: 16, 24, 64, 72, 80, 128, 256, 512), (128: 16, 64, 256),
+ * (192: 96), (256: 64, 128), (320: 168), (512: 80), (1024: 64, 128).
+ * lds_bytes in [0, the device's per-block LDS limit]; n_blocks in [1, 2^20];
+ * spin_us in [1, 100000]; records: device int64[4 n_blocks], caller-owned.
+ * Asynchronous on `stream` (the records are valid once it completes).
+ * Returns 0, -1 for an argument outside these sets (nothing launched) or -5
+ * on a HIP failure. */
+int32_t sa_rt_residency(int32_t block, int32_t vgprs, int32_t lds_bytes, int32_t n_blocks, int32_t spin_us,
+                        int64_t *records, int32_t *api_blocks_per_cu, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

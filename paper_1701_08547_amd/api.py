@@ -36,11 +36,11 @@ STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_ARG", -2: "SA_ERR_ALIGN", -3: "SA_ERR_NO
 EXPORTED = (
     "sa_status_string", "sa_last_error", "sa_arch_gfx950", "sa_arch_default_gfx950", "sa_arch_validate",
     "sa_workspace_bytes", "sa_occupancy", "sa_score", "sa_topk", "sa_set_tile",
-    "sa_plan_create", "sa_plan_destroy", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
+    "sa_plan_create", "sa_plan_destroy", "sa_plan_device_bytes", "sa_plan_bind", "sa_plan_layout", "sa_plan_info", "sa_plan_score", "sa_plan_topk",
     "sa_plan_autotune_workspace_bytes", "sa_plan_autotune", "sa_features", "sa_surrogate_fwd",
     "sa_surrogate_train_workspace_bytes", "sa_surrogate_train_step", "sa_surrogate_train_step_pairwise",
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure", "sa_rt_cpi",
-    "sa_rt_stream",
+    "sa_rt_stream", "sa_rt_residency",
     "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
     "sa_product_workspace_bytes", "sa_score_product",
 )
@@ -125,6 +125,10 @@ def lib():
             L.sa_plan_create.restype = i32
             L.sa_plan_destroy.argtypes = [vp]
             L.sa_plan_destroy.restype = i32
+            L.sa_plan_device_bytes.argtypes = [vp]
+            L.sa_plan_device_bytes.restype = sz
+            L.sa_plan_bind.argtypes = [vp, vp, sz, vp]
+            L.sa_plan_bind.restype = i32
             L.sa_plan_layout.argtypes = [vp, i64, i64, PS, P(i64), P(i64), P(i64), vp, vp, vp]
             L.sa_plan_layout.restype = i32
             L.sa_plan_info.argtypes = [vp, PS, P(i64), P(i64), P(sz)]
@@ -133,7 +137,7 @@ def lib():
             L.sa_plan_score.restype = i32
             L.sa_plan_topk.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
             L.sa_plan_topk.restype = i32
-            L.sa_plan_autotune_workspace_bytes.argtypes = [i64, i64, i32]
+            L.sa_plan_autotune_workspace_bytes.argtypes = [vp, i64, i64, i32]
             L.sa_plan_autotune_workspace_bytes.restype = sz
             L.sa_plan_autotune.argtypes = [vp, i64, i64, i32, P(SaArch), P(SaVariants), P(SaConfigs), vp, vp, vp, vp,
                                            vp, sz, vp, i32, PS, P(ctypes.c_float)]
@@ -177,6 +181,8 @@ def lib():
             L.sa_rt_cpi.restype = i32
             L.sa_rt_stream.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]
             L.sa_rt_stream.restype = i32
+            L.sa_rt_residency.argtypes = [i32, i32, i32, i32, i32, vp, P(i32), vp]
+            L.sa_rt_residency.restype = i32
             _lib = L
     return _lib
 
@@ -588,9 +594,11 @@ def plan_layout(seg, shape=None) -> dict:
 
 
 class Plan:
-    """A persistent-kernel plan for one CSR layout (sa_plan_*)."""
+    """A persistent-kernel plan for one CSR layout (sa_plan_*): the host
+    decomposition, bound to a device table this object allocates as a torch
+    buffer on `device` (the library allocates nothing)."""
 
-    def __init__(self, seg, k: int = 8, shape=None):
+    def __init__(self, seg, k: int = 8, shape=None, device=None, stream=None):
         sh = _seg_host(seg)
         self.n_var, self.n_evals, self.k = sh.shape[0] - 1, int(sh[-1]), int(k)
         h = ctypes.c_void_p()
@@ -604,6 +612,13 @@ class Plan:
                                   ctypes.byref(wb)))
         self.shape = (info_shape.tile, info_shape.items_per_lane, info_shape.waves_per_block)
         self.n_items, self.n_splits, self.workspace_bytes = ni.value, ns.value, wb.value
+        if device is None:
+            device = seg.device if hasattr(seg, "device") and seg.device.type == "cuda" else "cuda"
+        self.table = Workspace(int(lib().sa_plan_device_bytes(self._h)), device)
+        _check(lib().sa_plan_bind(self._h, self.table.ptr, self.table.nbytes, _stream(stream)))
+        # the copy reads this plan's host memory: let it finish here, so that
+        # closing the plan later never races it
+        (_torch().cuda.current_stream() if stream is None else stream).synchronize()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -684,7 +699,8 @@ def autotune(arch: dict, variants: dict, configs: dict, k: int = 8, reps: int = 
     if _sizes(variants, configs) != (n_var, n_evals):
         raise ValueError("configuration columns do not match seg")
     _check_outputs(o, n_evals, n_var, k)
-    ws = Workspace(int(lib().sa_plan_autotune_workspace_bytes(n_var, n_evals, k)), dev)
+    ws = Workspace(int(lib().sa_plan_autotune_workspace_bytes(sh.ctypes.data_as(ctypes.c_void_p), n_var, n_evals,
+                                                              int(k))), dev)
     best = SaPlanShape()
     ms = ctypes.c_float()
     a = _arch_struct(arch)

@@ -24,14 +24,17 @@ sa_status hip_fail(hipError_t e, const char *what);
 using sa_detail::fail;
 using sa_detail::hip_fail;
 
+// A plan owns no device memory: its decomposition lives here, on the host,
+// and sa_plan_bind copies it into a caller-provided device table.
 struct sa_plan {
   int64_t n_var = 0, n_evals = 0;
   int32_t k = 0;
   sa::PlanShape shape{};
   int64_t n_items = 0, n_splits = 0, n_slots = 0;
-  void *dev = nullptr;
-  sa::PlanDev pd{};
-  int device = 0;
+  std::vector<sa::PlanItem> items;
+  std::vector<sa::PlanWave> waves;
+  std::vector<sa::PlanSplit> splits;
+  sa::PlanDev pd{};  // pointers into the bound table (null until bound)
   int n_cu = 0;
 };
 
@@ -93,11 +96,32 @@ void decompose(const int64_t *seg, int64_t n_var, const sa::PlanShape &S, std::v
   }
 }
 
+// Byte offsets of the three arrays inside the device table.
+struct TableLayout {
+  size_t items, waves, splits, total;
+};
+
+TableLayout table_layout(const sa_plan *p) {
+  const size_t bi = p->items.size() * sizeof(sa::PlanItem), bw = p->waves.size() * sizeof(sa::PlanWave),
+               bs = p->splits.size() * sizeof(sa::PlanSplit);
+  TableLayout t;
+  t.items = 0;
+  t.waves = (bi + 255) / 256 * 256;
+  t.splits = t.waves + (bw + 255) / 256 * 256;
+  t.total = t.splits + (bs + 255) / 256 * 256;
+  if (t.total == 0) t.total = 256;
+  return t;
+}
+
+size_t fragment_bytes(const sa_plan *p) { return (size_t)p->n_slots * (size_t)p->k * sizeof(uint64_t); }
+
 sa_status plan_launch(const sa_plan *plan, sa::EvalLaunch &L, sa::Mode mode, bool has_grid, bool topk, void *workspace,
                       size_t workspace_bytes, hipStream_t stream) {
+  if (!plan->pd.items && plan->n_items > 0)
+    return fail(SA_ERR_ARG, "the plan has no device table: call sa_plan_bind first");
   L.k = topk ? plan->k : 0;
   if (topk) {
-    const size_t need = (size_t)plan->n_slots * (size_t)plan->k * sizeof(uint64_t);
+    const size_t need = fragment_bytes(plan);
     if (need > 0) {
       if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
       if ((uintptr_t)workspace % 256) return fail(SA_ERR_ALIGN, "workspace not 256-byte aligned");
@@ -176,61 +200,51 @@ sa_status sa_plan_create(const int64_t *seg_host, int64_t n_variants, int64_t n_
   if (!shape_ok(S))
     return fail(SA_ERR_ARG, "plan shape (tile %d, items %d, waves %d) outside {256k} x {1,2,4} x {4,8,16}", S.tile,
                 S.items, S.wpb);
-  int dev = 0, n_dev = 0;
-  if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0) return fail(SA_ERR_NODEV, "no HIP device");
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-
-  std::vector<sa::PlanItem> items;
-  std::vector<sa::PlanWave> waves;
-  std::vector<sa::PlanSplit> splits;
-  int64_t n_slots = 0;
-  decompose(seg_host, n_variants, S, items, waves, splits, n_slots);
-
-  const size_t bi = items.size() * sizeof(sa::PlanItem), bw = waves.size() * sizeof(sa::PlanWave),
-               bs = splits.size() * sizeof(sa::PlanSplit);
-  const size_t oi = 0, ow = (bi + 255) / 256 * 256, os = ow + (bw + 255) / 256 * 256;
-  const size_t total = os + bs + 256;
   sa_plan *p = new sa_plan();
+  decompose(seg_host, n_variants, S, p->items, p->waves, p->splits, p->n_slots);
   p->n_var = n_variants;
   p->n_evals = n_evals;
   p->k = k;
   p->shape = S;
-  p->n_items = (int64_t)items.size();
-  p->n_splits = (int64_t)splits.size();
-  p->n_slots = n_slots;
-  p->device = dev;
-  p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
-  e = hipMalloc(&p->dev, total);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(e, "hipMalloc (plan)");
-  }
-  char *base = (char *)p->dev;
-  if ((e = hipMemcpy(base + oi, items.data(), bi, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(base + ow, waves.data(), bw, hipMemcpyHostToDevice)) != hipSuccess ||
-      (bs && (e = hipMemcpy(base + os, splits.data(), bs, hipMemcpyHostToDevice)) != hipSuccess)) {
-    (void)hipFree(p->dev);
-    delete p;
-    return hip_fail(e, "hipMemcpy (plan)");
-  }
-  p->pd.items = (const sa::PlanItem *)(base + oi);
-  p->pd.waves = (const sa::PlanWave *)(base + ow);
-  p->pd.splits = (const sa::PlanSplit *)(base + os);
-  p->pd.n_items = p->n_items;
-  p->pd.n_splits = p->n_splits;
+  p->n_items = (int64_t)p->items.size();
+  p->n_splits = (int64_t)p->splits.size();
   *out = p;
   return SA_OK;
 }
 
+size_t sa_plan_device_bytes(const sa_plan *plan) { return plan ? table_layout(plan).total : 0; }
+
+sa_status sa_plan_bind(sa_plan *plan, void *table, size_t table_bytes, void *stream) {
+  if (!plan) return fail(SA_ERR_ARG, "plan is NULL");
+  if (!table) return fail(SA_ERR_ARG, "table is NULL");
+  if ((uintptr_t)table % 256) return fail(SA_ERR_ALIGN, "table not 256-byte aligned");
+  const TableLayout t = table_layout(plan);
+  if (table_bytes < t.total) return fail(SA_ERR_WORKSPACE, "table %zu bytes < %zu needed", table_bytes, t.total);
+  int dev = 0, n_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute");
+  char *base = (char *)table;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bi = plan->items.size() * sizeof(sa::PlanItem), bw = plan->waves.size() * sizeof(sa::PlanWave),
+               bs = plan->splits.size() * sizeof(sa::PlanSplit);
+  if ((bi && (e = hipMemcpyAsync(base + t.items, plan->items.data(), bi, hipMemcpyHostToDevice, s)) != hipSuccess) ||
+      (bw && (e = hipMemcpyAsync(base + t.waves, plan->waves.data(), bw, hipMemcpyHostToDevice, s)) != hipSuccess) ||
+      (bs && (e = hipMemcpyAsync(base + t.splits, plan->splits.data(), bs, hipMemcpyHostToDevice, s)) != hipSuccess))
+    return hip_fail(e, "hipMemcpyAsync (plan table)");
+  plan->n_cu = n_cu > 0 ? n_cu : 1;
+  plan->pd.items = (const sa::PlanItem *)(base + t.items);
+  plan->pd.waves = (const sa::PlanWave *)(base + t.waves);
+  plan->pd.splits = (const sa::PlanSplit *)(base + t.splits);
+  plan->pd.n_items = plan->n_items;
+  plan->pd.n_splits = plan->n_splits;
+  return SA_OK;
+}
+
 sa_status sa_plan_destroy(sa_plan *plan) {
-  if (!plan) return SA_OK;
-  hipError_t e = plan->dev ? hipFree(plan->dev) : hipSuccess;
   delete plan;
-  return e == hipSuccess ? SA_OK : hip_fail(e, "hipFree (plan)");
+  return SA_OK;
 }
 
 sa_status sa_plan_info(const sa_plan *plan, sa_plan_shape *shape, int64_t *n_items, int64_t *n_splits,
@@ -239,7 +253,7 @@ sa_status sa_plan_info(const sa_plan *plan, sa_plan_shape *shape, int64_t *n_ite
   if (shape) *shape = sa_plan_shape{plan->shape.tile, plan->shape.items, plan->shape.wpb};
   if (n_items) *n_items = plan->n_items;
   if (n_splits) *n_splits = plan->n_splits;
-  if (workspace_bytes) *workspace_bytes = (size_t)plan->n_slots * (size_t)plan->k * sizeof(uint64_t);
+  if (workspace_bytes) *workspace_bytes = fragment_bytes(plan);
   return SA_OK;
 }
 
@@ -294,12 +308,41 @@ sa_status sa_plan_topk(const sa_plan *plan, const float *keys, const int64_t *se
   return plan_launch(plan, L, sa::Mode::Keys, false, true, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
-size_t sa_plan_autotune_workspace_bytes(int64_t n_variants, int64_t n_evals, int32_t k) {
-  // kind-1 items of the smallest candidate shape bound the fragment slots
-  if (k <= 0 || n_evals <= 0) return 0;
-  (void)n_variants;
-  const int64_t smallest = 1024 * 4;
-  return (size_t)((n_evals + smallest - 1) / smallest + n_variants + 1) * (size_t)k * sizeof(uint64_t);
+}  // extern "C"
+
+namespace {
+
+const int32_t kTuneTiles[] = {1024, 2048, 4096, 8192};
+const int32_t kTuneItems[] = {1, 2, 4};
+const int32_t kTuneWaves[] = {4, 8, 16};
+
+// Largest fragment area and largest device table over the autotuner's
+// shapes (each 256-byte aligned): the workspace holds both, fragments first.
+sa_status tune_sizes(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k, size_t *frag,
+                     size_t *table) {
+  *frag = *table = 0;
+  for (int32_t t : kTuneTiles)
+    for (int32_t it : kTuneItems)
+      for (int32_t w : kTuneWaves) {
+        sa_plan_shape sh{t, it, w};
+        sa_plan *p = nullptr;
+        sa_status st = sa_plan_create(seg_host, n_variants, n_evals, k, &sh, &p);
+        if (st != SA_OK) return st;
+        *frag = std::max(*frag, (fragment_bytes(p) + 255) / 256 * 256);
+        *table = std::max(*table, table_layout(p).total);
+        sa_plan_destroy(p);
+      }
+  return SA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sa_plan_autotune_workspace_bytes(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k) {
+  size_t frag = 0, table = 0;
+  if (tune_sizes(seg_host, n_variants, n_evals, k, &frag, &table) != SA_OK) return 0;
+  return frag + table;
 }
 
 sa_status sa_plan_autotune(const int64_t *seg_host, int64_t n_variants, int64_t n_evals, int32_t k,
@@ -308,44 +351,48 @@ sa_status sa_plan_autotune(const int64_t *seg_host, int64_t n_variants, int64_t 
                            size_t workspace_bytes, void *stream, int32_t reps, sa_plan_shape *best, float *best_ms) {
   if (!best) return fail(SA_ERR_ARG, "best is NULL");
   if (reps < 1) reps = 3;
+  size_t frag_bytes = 0, table_bytes = 0;
+  sa_status st0 = tune_sizes(seg_host, n_variants, n_evals, k, &frag_bytes, &table_bytes);
+  if (st0 != SA_OK) return st0;
+  if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)workspace % 256) return fail(SA_ERR_ALIGN, "workspace not 256-byte aligned");
+  if (workspace_bytes < frag_bytes + table_bytes)
+    return fail(SA_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, frag_bytes + table_bytes);
+  void *table = (char *)workspace + frag_bytes;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SA_ERR_HIP, "hipEventCreate");
-  const int32_t tiles[] = {1024, 2048, 4096, 8192};
-  const int32_t items[] = {1, 2, 4};
-  const int32_t wpbs[] = {4, 8, 16};
   float best_t = 3.0e38f;
   sa_status result = SA_ERR_UNSUPPORTED;
-  for (int32_t t : tiles)
-    for (int32_t it : items)
-      for (int32_t w : wpbs) {
+  for (int32_t t : kTuneTiles)
+    for (int32_t it : kTuneItems)
+      for (int32_t w : kTuneWaves) {
         sa_plan_shape sh{t, it, w};
         sa_plan *p = nullptr;
         sa_status st = sa_plan_create(seg_host, n_variants, n_evals, k, &sh, &p);
+        if (st == SA_OK) st = sa_plan_bind(p, table, table_bytes, stream);
         if (st != SA_OK) {
+          sa_plan_destroy(p);
           result = st;
           goto done;
         }
-        size_t need = 0;
-        sa_plan_info(p, nullptr, nullptr, nullptr, &need);
-        if (need > workspace_bytes && (topk_idx || topk_val)) {
-          sa_plan_destroy(p);
-          continue;
-        }
         st = sa_plan_score(p, arch, variants, configs, score, occ_waves, topk_idx, topk_val, workspace,
-                           workspace_bytes, stream);  // warm-up
+                           frag_bytes, stream);  // warm-up
         std::vector<float> ts;
         for (int r = 0; st == SA_OK && r < reps; ++r) {
           (void)hipEventRecord(e0, s);
           st = sa_plan_score(p, arch, variants, configs, score, occ_waves, topk_idx, topk_val, workspace,
-                             workspace_bytes, stream);
+                             frag_bytes, stream);
           (void)hipEventRecord(e1, s);
           (void)hipEventSynchronize(e1);
           float ms = 0.f;
           (void)hipEventElapsedTime(&ms, e0, e1);
           ts.push_back(ms);
         }
+        // the table's upload and every launch reading it have finished
+        // before the plan (the upload's host source) goes away
+        (void)hipStreamSynchronize(s);
         sa_plan_destroy(p);
         if (st != SA_OK) {
           result = st;

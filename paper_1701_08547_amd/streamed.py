@@ -66,7 +66,7 @@ class Streamed:
         ws_plain = 0
         for v0, v1 in self.chunks:
             local = (seg[v0:v1 + 1] - seg[v0]).astype(np.int64)
-            plan = api.Plan(local, k=self.k, shape=shape)
+            plan = api.Plan(local, k=self.k, shape=shape, device=self.dev)
             self.plans.append(plan)
             self.segs.append(torch.from_numpy(local).to(self.dev))
             ws_plain = max(ws_plain, plan.workspace_bytes)

@@ -185,6 +185,53 @@ def test_train_step_gradients_and_adam(n):
     assert np.array_equal(w2, mlp.bf16(cur["W2"].reshape(-1)))
 
 
+def test_adam_over_consecutive_steps():
+    """Six consecutive training steps (t = 1..6, squared error and then the
+    pairwise loss): before each step the device state (master, m, v) is read,
+    and after it the update must equal Adam's binary64 definition at that t,
+    fed with the gradient the step returned.  Catches beta1/beta2 mixed up and
+    a bias correction that does not follow t."""
+    arch = oracle.arch_cdna4()
+    b = feature_batch(71, [2200])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:2048]
+    p, mean, inv, s = surrogate(13, f)
+    rng = np.random.default_rng(5)
+    target = (0.4 * np.tanh(f[:, 22] - f[:, 22].mean()) + 0.05 * rng.standard_normal(f.shape[0])).astype(np.float32)
+    ft, tt = torch.from_numpy(f).cuda(), torch.from_numpy(target).cuda()
+    lr = 2e-3
+    for t in range(1, 7):
+        group = 0 if t <= 3 else 64
+        master0, m0, v0 = (x.cpu().numpy().astype(np.float64) for x in (s.master, s.m, s.v))
+        say("adam step", t, "group", group)
+        s.train_step(ft, tt, lr=lr, group=group)
+        torch.cuda.synchronize()
+        grad = s.grad.cpu().numpy().astype(np.float64)
+        state = {"t": t - 1}
+        for k, vals in (("m_", m0), ("v_", v0)):
+            for name, arr in api.params_from_flat(vals).items():
+                state[k + name] = np.asarray(arr, np.float64)
+        new = mlp.adam_step(api.params_from_flat(master0), {k: np.asarray(x, np.float64) for k, x in
+                                                             api.params_from_flat(grad).items()}, state, lr=lr)
+        assert state["t"] == t and s.step_count == t
+        cur = api.params_from_flat(s.master.cpu().numpy())
+        m1 = api.params_from_flat(s.m.cpu().numpy())
+        v1 = api.params_from_flat(s.v.cpu().numpy())
+        for k in NAMES:
+            want = np.asarray(new[k], np.float64)
+            d = np.abs(np.asarray(cur[k], np.float64) - want)
+            assert np.all(d <= 2e-7 + 2 ** -22 * np.abs(want)), (t, k, d.max())
+            # binary32 moments: a few roundings of each term, and the binary32
+            # constants 0.9f and 1 - 0.999f (the latter 1.3e-5 below 0.001)
+            g = np.asarray(api.params_from_flat(grad)[k], np.float64)
+            mp, vp = (np.asarray(api.params_from_flat(x)[k], np.float64) for x in (m0, v0))
+            m_tol = 2 ** -20 * (0.9 * np.abs(mp) + 0.1 * np.abs(g)) + 1e-30
+            v_tol = 2 ** -20 * 0.999 * vp + 2e-5 * 1e-3 * g * g + 1e-30
+            assert np.all(np.abs(np.asarray(m1[k], np.float64) - state["m_" + k]) <= m_tol), (t, k)
+            assert np.all(np.abs(np.asarray(v1[k], np.float64) - state["v_" + k]) <= v_tol), (t, k)
+        # the update moved the weights at every step (the loss has a gradient)
+        assert np.abs(np.asarray(cur["W2"], np.float64) - api.params_from_flat(master0)["W2"]).max() > 0
+
+
 def test_training_reduces_loss():
     arch = oracle.arch_cdna4()
     b = feature_batch(40, [6000])

@@ -1,0 +1,94 @@
+"""The CDNA4 constants of the occupancy bound (Sec. III-A, Eqs. 1-5; Table I's
+per-multiprocessor limits), pinned on the device.
+
+Probe kernels that own exactly R registers per lane run with S bytes of LDS
+in workgroups of T threads; the workgroups one compute unit holds at once,
+times the waves per workgroup, is the measured W*.  It must equal the
+oracle's W* under the CDNA4 descriptor: the register ladder at T = 64 fixes
+the register file and its granule (64/72/80/128/256/512 registers -> 32, 28,
+24, 16, 8 and 4 waves), S = 5,376 at T = 64 fixes the LDS granule (29 with
+512-byte granules, 30 with 256), T = 64 with nothing limiting fixes whether
+one-wave workgroups count against the 16-workgroup limit (32 or 16), and the
+hand-worked cases of the oracle's pins are repeated as launches.  HIP's own
+occupancy API is recorded beside each case; where it disagrees with the
+probe, the probe (what the hardware did) decides.
+"""
+import json
+import os
+import sys
+
+import pytest
+
+import oracle
+from paper_1701_08547_amd import probe
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+# (T, R, S): register ladder, LDS ladder, the hand-worked cases
+CASES = [(64, 64, 0), (64, 72, 0), (64, 80, 0), (64, 128, 0), (64, 256, 0), (64, 512, 0),
+         (64, 16, 0), (64, 24, 0), (128, 16, 0), (100, 16, 0), (128, 64, 0), (128, 256, 0),
+         (64, 16, 5376), (64, 16, 5632), (64, 16, 40960), (64, 16, 65536), (64, 16, 20000),
+         (256, 64, 0), (256, 128, 0), (1024, 128, 0), (1024, 64, 0), (192, 96, 0), (512, 80, 20000),
+         (320, 168, 0), (128, 16, 12288), (256, 64, 32768)]
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def say(*a):
+    print("[residency]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def device_arch():
+    from paper_1701_08547_amd import api
+
+    a = api.arch_default(0)
+    say("device descriptor", json.dumps(a, sort_keys=True))
+    return a
+
+
+@pytest.fixture(scope="module")
+def results(device_arch):
+    got = []
+    lds_max = device_arch["max_lds_per_block"]
+    for T, R, S in CASES + [(64, 16, lds_max)]:
+        say("probe T=%d R=%d S=%d" % (T, R, S))
+        r = probe.residency(T, R, S, device_arch["n_cu"])
+        r["oracle_W"] = oracle.occupancy(oracle.arch_cdna4(), T, R, S)
+        r.pop("per_cu")
+        say(json.dumps(r, sort_keys=True))
+        got.append(r)
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "residency_probe.json"), "w") as f:
+        json.dump({"device_arch": device_arch, "cases": got}, f, indent=1, sort_keys=True)
+    return got
+
+
+def test_probe_sees_every_compute_unit(results, device_arch):
+    for r in results:
+        assert r["cus"] == device_arch["n_cu"], r
+
+
+def test_measured_occupancy_equals_the_oracle(results):
+    bad = [r for r in results if r["max"] * r["waves_per_block"] != r["oracle_W"]]
+    assert not bad, json.dumps(bad, indent=1)
+
+
+def test_every_compute_unit_reaches_the_bound(results):
+    """The bound is reached on every CU, not only on one (the dispatcher
+    fills each unit)."""
+    bad = [r for r in results if r["min"] != r["max"]]
+    assert not bad, json.dumps(bad, indent=1)
+
+
+def test_device_descriptor_matches_the_constants(device_arch):
+    """The device-queried descriptor agrees with the CDNA4 constants the
+    oracle uses (compute units, wave size, thread and LDS limits)."""
+    ora = oracle.arch_cdna4()
+    for f in ("wave_size", "max_threads_per_block", "lds_per_cu", "max_lds_per_block", "max_waves_per_cu"):
+        assert device_arch[f] == ora[f], (f, device_arch[f], ora[f])

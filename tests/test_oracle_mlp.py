@@ -81,6 +81,67 @@ def test_adam_first_step_is_sign_of_gradient_times_lr():
     assert np.allclose(out["w"], want.astype(np.float32), rtol=0, atol=1e-7)
 
 
+def _adam_run(p, grads, lr=1e-3):
+    st = {}
+    seq = []
+    for g in grads:
+        p = mlp.adam_step(p, {"w": g}, st, lr=lr)
+        seq.append(p["w"].astype(np.float64))
+    return seq, st
+
+
+def test_adam_three_steps_closed_form():
+    """Three steps in closed form (Adam's definition with bias correction at
+    every step t).  A constant gradient g moves each weight by lr g / (|g| +
+    eps) at every step (m_hat = g, v_hat = g^2 for all t); a frozen t = 1
+    correction would give (1 - b1^2)/(1 - b1) / sqrt((1 - b2^2)/(1 - b2)) =
+    1.344 times that at t = 2.  The alternating sequence g, -g, g gives m_hat
+    = g, -(1 - b1)/(1 + b1) g, (1 - b1 + b1^2)/(1 + b1 + b1^2) g with v_hat =
+    g^2 throughout; swapping b1 and b2 turns the second factor 1/19 into
+    1/1999."""
+    lr, b1, eps = 1e-3, 0.9, 1e-8
+    w0 = np.array([1.0, -2.0, 0.5, 0.0], np.float32)
+    g = np.array([0.3, -4.0, 1e-3, 2.5])
+    step = lr * g / (np.abs(g) + eps)
+    seq, st = _adam_run({"w": w0}, [g, g, g], lr=lr)
+    for t in range(3):
+        assert np.allclose(seq[t], w0 - (t + 1) * step, rtol=0, atol=2e-7), t
+    assert st["t"] == 3
+    assert np.allclose(st["m_w"], (1 - b1 ** 3) * g, rtol=1e-12, atol=0)
+    assert np.allclose(st["v_w"], (1 - 0.999 ** 3) * g * g, rtol=1e-12, atol=0)
+    factors = [1.0, -(1 - b1) / (1 + b1), (1 - b1 + b1 * b1) / (1 + b1 + b1 * b1)]
+    assert abs(factors[1] + 1 / 19) < 1e-15 and abs(factors[2] - 91 / 271) < 1e-15
+    seq, st = _adam_run({"w": w0}, [g, -g, g], lr=lr)
+    want = w0.astype(np.float64)
+    for t in range(3):
+        want = want - lr * factors[t] * g / (np.abs(g) + eps)
+        assert np.allclose(seq[t], want, rtol=0, atol=3e-7), t
+
+
+def test_adam_planted_mistakes_fail_the_closed_form():
+    """The closed form above tells Adam from its two plausible mistakes:
+    beta1/beta2 swapped, and the bias correction frozen at t = 1."""
+    lr, eps = 1e-3, 1e-8
+    g = np.array([0.3, -4.0, 2.5])
+
+    def wrong(seq_g, b1, b2, frozen):
+        m = v = np.zeros(3)
+        w = np.zeros(3)
+        for t, gt in enumerate(seq_g, start=1):
+            m = b1 * m + (1 - b1) * gt
+            v = b2 * v + (1 - b2) * gt * gt
+            tc = 1 if frozen else t
+            w = w - lr * (m / (1 - b1 ** tc)) / (np.sqrt(v / (1 - b2 ** tc)) + eps)
+        return w
+
+    right = wrong([g, -g], 0.9, 0.999, False)
+    assert np.allclose(right, -lr * (1 - 1 / 19) * g / (np.abs(g) + eps), rtol=0, atol=1e-12)
+    assert np.abs(wrong([g, -g], 0.999, 0.9, False) - right).min() > 4e-5
+    assert np.abs(wrong([g, g], 0.9, 0.999, True) - wrong([g, g], 0.9, 0.999, False)).min() > 3e-4
+    seq, _ = _adam_run({"w": np.zeros(3, np.float32)}, [g, -g])
+    assert np.allclose(seq[-1], right, rtol=0, atol=2e-7)
+
+
 def test_ranking_metrics():
     scipy_stats = pytest.importorskip("scipy.stats")
     g = np.random.default_rng(1)

@@ -106,3 +106,47 @@ def test_invalid_offsets_rejected():
         api.plan_layout(np.array([0, 10], np.int64), (1000, 4, 4))  # tile not a multiple of 256
     with pytest.raises(api.SAError):
         api.plan_layout(np.array([0, 10], np.int64), (1024, 3, 4))
+
+
+def test_plan_is_a_host_object_bound_to_a_caller_table():
+    """sa_plan_create makes no HIP call (it runs here without a device);
+    the device table is the caller's, sized by sa_plan_device_bytes, and
+    sa_plan_bind checks it before any copy."""
+    L = api.lib()
+    seg = np.array([0, 5000, 5000, 70000, 70100], np.int64)
+    h = api.ctypes.c_void_p()
+    assert L.sa_plan_create(seg.ctypes.data_as(api.ctypes.c_void_p), 4, 70100, 8, None, api.ctypes.byref(h)) == 0
+    lay = api.plan_layout(seg)
+    nbytes = L.sa_plan_device_bytes(h)
+    want = sum((b + 255) // 256 * 256 for b in (len(lay["items"]) * 16, lay["waves"].shape[0] * 4 * 32,
+                                                  len(lay["splits"]) * 32))
+    assert nbytes == want and nbytes % 256 == 0
+    assert L.sa_plan_device_bytes(None) == 0
+    assert L.sa_plan_bind(h, None, nbytes, None) == -1                                    # NULL table
+    assert L.sa_plan_bind(h, api.ctypes.c_void_p(4096 + 64), nbytes, None) == -2          # not 256-byte aligned
+    assert L.sa_plan_bind(h, api.ctypes.c_void_p(4096), nbytes - 1, None) == -4           # too small
+    assert L.sa_plan_bind(None, api.ctypes.c_void_p(4096), nbytes, None) == -1
+    # an unbound plan is refused before any launch
+    assert L.sa_plan_topk(h, api.ctypes.c_void_p(256), api.ctypes.c_void_p(256), api.ctypes.c_void_p(256), None,
+                          api.ctypes.c_void_p(256), 1 << 20, None) == -1
+    assert "sa_plan_bind" in L.sa_last_error().decode()
+    assert L.sa_plan_destroy(h) == 0
+    # the autotuner's workspace: largest fragment area + largest table over its shapes
+    ws = L.sa_plan_autotune_workspace_bytes(seg.ctypes.data_as(api.ctypes.c_void_p), 4, 70100, 8)
+    assert ws >= nbytes and ws % 256 == 0
+    bad = np.array([0, 5, 3], np.int64)
+    assert L.sa_plan_autotune_workspace_bytes(bad.ctypes.data_as(api.ctypes.c_void_p), 2, 3, 8) == 0
+
+
+def test_library_sources_never_allocate_device_memory():
+    """The library allocates no device memory: no allocation or free call
+    appears in its sources (buffers are the caller's)."""
+    import os
+    import re
+
+    csrc = os.path.join(os.path.dirname(api.__file__), "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            src = open(os.path.join(csrc, name)).read()
+            assert not re.search(r"\bhip(Malloc|MallocAsync|Free|FreeAsync|HostMalloc|MallocManaged|ExtMallocWithFlags)\s*\(",
+                                 src), name
