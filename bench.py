@@ -29,6 +29,19 @@ Prints ONE JSON line (rank 0):
   stream_ceiling  a pure stream of the same 24 B per evaluation with no model
                arithmetic (fastest of a sweep of launch shapes): the practical
                memory ceiling of the plain pass on this device
+  cold         the same pass rotating over three copies of the workload
+               (columns and outputs, 1.18 GB), so that no launch finds its
+               inputs in the 256 MB last-level cache
+  c2           10,000 variants with search spaces log-uniform in
+               [64, 262,144] (3.2e8 evaluations), top-16: one planned launch at
+               the autotuner's shape, K launches as one graph
+  c4           100,000 variants with spaces log-uniform in [256, 2^20]
+               (1.26e10 evaluations), rows generated on the device per chunk:
+               the plain and the corrected pass side by side, one pass each
+
+The timed plan shape of the headline is the one the committed counters were
+taken at (--shape); the autotuner's pick on the same batch is reported
+beside it.
 """
 from __future__ import annotations
 
@@ -46,13 +59,10 @@ HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # 157.3 TFLOP/s FP32 vector peak, a fused multiply-add counting two: lane operations per second
 VALU_PEAK_LANE_OPS = 157.3e12 / 2
-MLP_FLOP_PER_EVAL = 2 * (32 * 128 + 128 * 128 + 128)
+# algorithmic dense work per evaluation: 24->128->128->1 (the K padding to 32 is not counted)
+MLP_FLOP_PER_EVAL = 2 * (24 * 128 + 128 * 128 + 128)
 BYTES_PER_EVAL = 24
 K = 8
-# sources the planned scoring kernel is built from
-PLAIN_KERNEL_SOURCES = ("sa_internal.h", "sa_dev.h", "sa_eval.hip", "sa_plan.hip")
-
-
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -76,21 +86,22 @@ def parse():
     p.add_argument("--cpu-baseline-batches", action="store_true",
                    help="host only: the cpu_baseline leg (the CPU oracle) on every batch shape, one thread and all "
                         "threads (no GPU work)")
-    p.add_argument("--shape", default=None, help="tile,items,waves: fixed plan shape, no autotuning")
+    p.add_argument("--shape", default=None,
+                   help="tile,items,waves of the timed plan ('auto': the autotuner's pick); default: the shape the "
+                        "committed traffic counters were taken at")
+    p.add_argument("--no-autotune", action="store_true", help="skip the autotuner run beside the headline")
+    p.add_argument("--cold-steps", type=int, default=30, help="timed launches of the cold-cache leg (0: skip)")
+    p.add_argument("--c2-steps", type=int, default=20, help="timed launches of the 10,000-variant leg (0: skip)")
+    p.add_argument("--c4", type=int, default=1, help="run the 100,000-variant streamed leg (0: skip)")
     return p.parse_args()
 
 
 def source_digest() -> str:
     """Digest of the kernel sources: a traffic figure measured for other
     sources is not reported."""
-    import hashlib
+    from paper_1701_08547_amd import build
 
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1701_08547_amd", "csrc")
-    for name in PLAIN_KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
+    return build.plain_kernel_digest()
 
 
 def copy_calibration():
@@ -209,9 +220,9 @@ def main():
         "idx": torch.empty((n_var, K), dtype=torch.int32, device=dev),
         "val": torch.empty((n_var, K), dtype=torch.float32, device=dev),
     }
-    if args.shape:
-        shape, tune_ms = tuple(int(x) for x in args.shape.split(",")), None
-    else:
+    counted = counted_shape(args.traffic)
+    tune = None
+    if args.shape == "auto" or not (args.no_autotune or args.only_plain):
         # bring the clocks up before the autotuner measures anything
         plan0 = api.Plan(batch.seg, k=K)
         ws0 = api.Workspace(plan0.workspace_bytes, dev)
@@ -219,7 +230,15 @@ def main():
         while time.perf_counter() - t0 < 0.5:
             plan0.score(arch, var, cfg, outputs=outs, workspace=ws0)
         torch.cuda.synchronize()
-        shape, tune_ms = api.autotune(arch, var, cfg, k=K, reps=10, outputs=outs)
+        pick, tune_ms = api.autotune(arch, var, cfg, k=K, reps=10, outputs=outs)
+        tune = {"pick": {"tile": pick[0], "items_per_lane": pick[1], "waves_per_block": pick[2]},
+                "median_ms": tune_ms}
+    if args.shape == "auto":
+        shape = pick
+    elif args.shape:
+        shape = tuple(int(x) for x in args.shape.split(","))
+    else:
+        shape = counted or (8192, 1, 4)
     plan = api.Plan(batch.seg, k=K, shape=shape)
     ws = api.Workspace(plan.workspace_bytes, dev)
 
@@ -257,20 +276,16 @@ def main():
     value = n_evals * args.steps / wall
     achieved = BYTES_PER_EVAL * n_evals / (mean_ms * 1e-3) / 1e9
     traffic = None
-    if os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            t = json.load(f)
-        if t.get("source_digest") == source_digest():
-            traffic = t.get("bytes_per_launch")
+    t = counter_record(args.traffic, shape)
+    if t is not None:
+        traffic = t.get("bytes_per_launch")
     valu_side = None
-    if os.path.exists(args.valu):
-        with open(args.valu) as f:
-            vc = json.load(f)
-        if vc.get("source_digest") == source_digest():
-            lane_ops = vc["valu_wave_insts_per_launch"] * 64 / (mean_ms * 1e-3)
-            valu_side = {"lane_ops_per_s": lane_ops, "peak": VALU_PEAK_LANE_OPS, "frac": lane_ops / VALU_PEAK_LANE_OPS,
-                         "wave_insts_per_eval": vc["valu_wave_insts_per_launch"] / n_evals,
-                         "note": "SQ_INSTS_VALU counted at plan shape (8192,1,4) x 64 lanes / event time per launch"}
+    vc = counter_record(args.valu, shape)
+    if vc is not None:
+        lane_ops = vc["valu_wave_insts_per_launch"] * 64 / (mean_ms * 1e-3)
+        valu_side = {"lane_ops_per_s": lane_ops, "peak": VALU_PEAK_LANE_OPS, "frac": lane_ops / VALU_PEAK_LANE_OPS,
+                     "wave_insts_per_eval": vc["valu_wave_insts_per_launch"] / n_evals,
+                     "note": "SQ_INSTS_VALU counted at the timed plan shape x 64 lanes / event time per launch"}
 
     line = {
         "metric": METRIC,
@@ -293,7 +308,7 @@ def main():
             "k": K,
             "mode": "plain",
             "plan_shape": {"tile": shape[0], "items_per_lane": shape[1], "waves_per_block": shape[2]},
-            "autotune_ms": tune_ms,
+            "autotune": tune,
         },
         "roofline": {
             "bound": "hbm",
@@ -302,8 +317,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_note": "FETCH_SIZE + WRITE_SIZE per launch, counted at plan shape (8192,1,4), scaled by a "
-                            "plain copy; null once the kernel sources differ from the counted ones",
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE per launch at the timed plan shape, scaled by a plain copy; "
+                            "null once the kernel sources differ from the counted ones",
             "kernel": "sa_plan_kernel, one launch per step (HIP events around the K-launch graph replay)",
             "event_ms_mean": mean_ms,
             "valu_side": valu_side,
@@ -318,9 +333,165 @@ def main():
         if args.product_steps > 0:
             line["product"] = product_leg(arch, var, n_var, n_evals, outs, args.product_steps)
         line["stream_ceiling"] = stream_ceiling(cfg, n_evals, achieved)
+        if args.cold_steps > 0:
+            line["cold"] = cold_leg(arch, var, cfg, plan, n_var, n_evals, args.cold_steps)
+        if args.c2_steps > 0:
+            line["c2"] = c2_leg(arch, args.c2_steps)
+        if args.c4:
+            line["c4"] = c4_leg(arch, sur)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def counted_shape(path: str):
+    """The plan shape the committed counters were taken at, when they match
+    the current kernel sources."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_digest") != source_digest() or "shape" not in t:
+        return None
+    return tuple(int(x) for x in t["shape"])
+
+
+def counter_record(path: str, shape):
+    """A committed counter record, if it was taken on the current kernel
+    sources at this plan shape."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_digest") != source_digest() or tuple(t.get("shape", ())) != tuple(shape):
+        return None
+    return t
+
+
+def _graph_ms(fn, steps: int) -> float:
+    """Mean milliseconds per call of `fn` over `steps` calls captured in one
+    HIP graph (after three eager warm-up calls and one untimed replay)."""
+    import torch
+
+    for _ in range(3):
+        fn(0)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(steps):
+            fn(i)
+    graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cold_leg(arch, var, cfg, plan, n_var: int, n_evals: int, steps: int, copies: int = 3) -> dict:
+    """The headline pass rotating over `copies` copies of the configuration
+    columns and of the outputs: each launch reads and writes 393 MB that the
+    previous launches did not touch, so the 256 MB last-level cache cannot
+    hold them."""
+    import torch
+
+    from paper_1701_08547_amd import api
+
+    dev = cfg["seg"].device
+    cfgs, outs = [], []
+    for _ in range(copies):
+        c = {"seg": cfg["seg"]}
+        for f in ("block", "unroll", "regs", "grid"):
+            c[f] = cfg[f].clone()
+        cfgs.append(c)
+        outs.append({"occ": torch.empty(n_evals, dtype=torch.int32, device=dev),
+                     "score": torch.empty(n_evals, dtype=torch.float32, device=dev),
+                     "idx": torch.empty((n_var, K), dtype=torch.int32, device=dev),
+                     "val": torch.empty((n_var, K), dtype=torch.float32, device=dev)})
+    ws = api.Workspace(plan.workspace_bytes, dev)
+    ms = _graph_ms(lambda i: plan.score(arch, var, cfgs[i % copies], outputs=outs[i % copies], workspace=ws), steps)
+    gbs = BYTES_PER_EVAL * n_evals / (ms * 1e-3) / 1e9
+    return {"value": n_evals / (ms * 1e-3), "unit": "configs/s", "ms_per_step": ms, "steps": steps,
+            "copies": copies, "working_set_bytes": copies * BYTES_PER_EVAL * n_evals, "GBps": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+
+
+def c2_leg(arch, steps: int) -> dict:
+    """10,000 variants, search spaces log-uniform in [64, 262,144], top-16
+    fused, no per-evaluation outputs: the autotuner picks the plan shape, then
+    `steps` launches replay as one graph.  Algorithmic bytes: 16 per
+    evaluation read, 44 + 8 k per variant."""
+    import torch
+
+    from paper_1701_08547_amd import api, workloads
+
+    t0 = time.perf_counter()
+    b = workloads.c2(n_cu=arch["n_cu"])
+    var, cfg = api.device_batch(b)
+    k = 16
+    dev = cfg["seg"].device
+    out = {"idx": torch.empty((b.n_var, k), dtype=torch.int32, device=dev),
+           "val": torch.empty((b.n_var, k), dtype=torch.float32, device=dev)}
+    shape, tune_ms = api.autotune(arch, var, cfg, k=k, reps=5, outputs=out, want_score=False, want_occ=False)
+    plan = api.Plan(b.seg, k=k, shape=shape)
+    ws = api.Workspace(plan.workspace_bytes, dev)
+    ms = _graph_ms(lambda i: plan.score(arch, var, cfg, want_score=False, want_occ=False, outputs=out, workspace=ws),
+                   steps)
+    nbytes = 16 * b.n_evals + (44 + 8 * k) * b.n_var
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": "10,000 variants, search spaces log-uniform in [64, 262144], top-16, no per-evaluation "
+                        "outputs", "n_evals": b.n_evals, "value": b.n_evals / (ms * 1e-3), "unit": "configs/s",
+            "ms_per_step": ms, "steps": steps, "plan_shape": list(shape), "autotune_ms": tune_ms,
+            "algorithmic_bytes": nbytes, "GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "seconds": time.perf_counter() - t0}
+
+
+def c4_leg(arch, sur) -> dict:
+    """100,000 variants, spaces log-uniform in [256, 2^20] (1.26e10
+    evaluations), rows generated on the device in chunks of whole segments:
+    one pass of generation alone, one of generation + plain top-16 and one of
+    generation + corrected top-16; the plain and corrected figures subtract
+    the generation time."""
+    import numpy as np
+    import torch
+
+    from paper_1701_08547_amd import api, streamed, workloads
+
+    t0 = time.perf_counter()
+    if sur is None:
+        from paper_1701_08547_amd import correction
+
+        sur = api.Surrogate(correction.init_params(0), np.zeros(24, np.float32), np.ones(24, np.float32))
+    batch = workloads.c4(n_cu=arch["n_cu"])
+    st = streamed.Streamed(batch, arch, k=16, chunk_evals=1 << 28, surrogate=sur, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    st.run(plain=True, corrected=False)  # warm-up: first launches of every chunk's plan
+    t_gen = timed(lambda: [st.generate(i) for i in range(len(st.chunks))])
+    t_plain = timed(lambda: st.run(plain=True, corrected=False)) - t_gen
+    t_corr = timed(lambda: st.run(plain=False, corrected=True)) - t_gen
+    n = batch.n_evals
+    return {"workload": "100,000 variants, spaces log-uniform in [256, 1048576], rows generated on the device",
+            "n_evals": n, "chunks": len(st.chunks), "k": 16, "generate_ms": t_gen,
+            "plain": {"ms": t_plain, "value": n / (t_plain * 1e-3), "unit": "configs/s",
+                      "read_GBps": 16 * n / (t_plain * 1e-3) / 1e9,
+                      "frac_of_hbm_peak": 16 * n / (t_plain * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "corrected": {"ms": t_corr, "value": n / (t_corr * 1e-3), "unit": "configs/s",
+                          "TFLOPs": MLP_FLOP_PER_EVAL * n / (t_corr * 1e-3) / 1e12,
+                          "frac_of_bf16_peak": MLP_FLOP_PER_EVAL * n / (t_corr * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS},
+            "seconds": time.perf_counter() - t0}
 
 
 def stream_ceiling(cfg, n_evals: int, achieved: float) -> dict:
@@ -447,7 +618,8 @@ def corrected_leg(arch, var, cfg, n_var, n_evals, sur, steps: int) -> dict:
             "kernels": "sa_corrected_kernel + sa_merge_kernel",
             "roofline": {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
-                         "note": "41,216 FLOP per evaluation (24->128->128->1, inputs padded to 32); "
+                         "note": "39,168 algorithmic FLOP per evaluation (24->128->128->1; the padding of the inputs "
+                                 "to 32 is not counted); "
                                  "bound by vector issue, not by the matrix cores: the table GELU between the layers is three quarters of the vector instructions, and a SIMD issues for about 86 % of the launch (SQ counters)"}}
 
 

@@ -118,7 +118,9 @@ int32_t sa_rt_stream(int64_t n, const int32_t *c0, const int32_t *c1, const int3
  * answer, hipOccupancyMaxActiveBlocksPerMultiprocessor, for the same
  * kernel, block size and LDS.  Supported (block rounded up to a multiple of
  * 64, vgprs): (64: 16, 24, 64, 72, 80, 128, 256, 512), (128: 16, 64, 256),
- * (192: 96), (256: 64, 128), (320: 168), (512: 80), (1024: 64, 128).
+ * (192: 16, 96, 168), (256: 64, 128), (320: 16, 96, 168), (384: 16, 128),
+ * (448: 16), (512: 80), (576: 16), (640: 16), (768: 16), (960: 16),
+ * (1024: 64, 128).
  * lds_bytes in [0, the device's per-block LDS limit]; n_blocks in [1, 2^20];
  * spin_us in [1, 100000]; records: device int64[4 n_blocks], caller-owned.
  * Asynchronous on `stream` (the records are valid once it completes).

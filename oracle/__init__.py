@@ -62,14 +62,17 @@ def arch_cdna4() -> dict:
     """CDNA4 (gfx950, MI355X) descriptor as the oracle reads the paper's
     Table I rows on that part: 256 CUs, wave64, 8 wave slots on each of 4
     SIMDs, a 512-register unified VGPR/AGPR file per SIMD lane (granule 8),
-    160 KiB of LDS per CU (granule 512 B), at most 16 multi-wave workgroups
-    per CU.  Instruction weights follow Table II's convention (CPI = 1/IPC,
+    160 KiB of LDS per CU allocated in 1,280-byte granules, at most 16
+    multi-wave workgroups per CU (one-wave workgroups exempt).  The register,
+    wave-slot, LDS-granule and workgroup-limit values were measured on the
+    device by the residency probe (workgroups resident at once per CU for
+    probe kernels of known register and LDS use).  Instruction weights follow Table II's convention (CPI = 1/IPC,
     FP32 IPC = lanes per CU) with 64 lanes per CU: 2^-6 for fp and int ops,
     2^-4 for memory, control and barrier, 2^-5 for register moves."""
     return dict(
         n_cu=256, wave_size=64, max_threads_per_block=1024, max_waves_per_cu=32,
         max_blocks_per_cu=16, single_wave_exempt=1, simd_per_cu=4, vgprs_per_simd_lane=512,
-        vgpr_granule=8, max_vgprs_per_thread=512, lds_per_cu=163840, lds_granule=512,
+        vgpr_granule=8, max_vgprs_per_thread=512, lds_per_cu=163840, lds_granule=1280,
         max_lds_per_block=163840, w_sat=32, max_unroll=64, max_grid=262144,
         cpi_fp=2.0 ** -6, cpi_int=2.0 ** -6, cpi_mem=2.0 ** -4, cpi_ctrl=2.0 ** -4,
         cpi_sync=2.0 ** -4, cpi_reg=2.0 ** -5,

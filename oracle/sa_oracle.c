@@ -28,6 +28,15 @@
  *     with `vgprs_per_simd_lane` registers per lane and
  *     max_waves_per_cu / simd_per_cu wave slots; a wave takes its register
  *     count rounded up to `vgpr_granule` on one partition.
+ *   - How a block's waves share the partitions (Eqs. 3 and 4 count a
+ *     multiprocessor's warps as one pool; a partitioned unit needs a rule):
+ *     a block of at most simd_per_cu waves puts each wave on a different
+ *     partition, so the partitions' wave places pool; a larger block is
+ *     admitted only while every partition has ceil(W_B / simd_per_cu) free
+ *     places, and its waves then go round-robin over the partitions.  With
+ *     w places per partition the latter admits floor(P (w - c) / W_B) + 1
+ *     blocks (P partitions, c = ceil(W_B / P), w >= c).  With one partition
+ *     both reduce to the pooled floor(w / W_B).
  *   - Eq. 5 takes a floor (a ceiling would admit more LDS than exists); the
  *     allocation is rounded up to `lds_granule`.
  *   - Registers = 0 or LDS = 0 means "this resource does not limit" (the
@@ -104,23 +113,31 @@ static int or_variant_valid(int32_t n_fp, int32_t n_int, int32_t n_ld, int32_t n
   return 1;
 }
 
+/* Blocks of W_B waves that partitions with w wave places each admit. */
+static int64_t or_blocks_on_partitions(const oracle_arch *a, int64_t w, int64_t W_B) {
+  int64_t P = a->simd_per_cu;
+  if (W_B <= P) return (P * w) / W_B;
+  int64_t c = or_ceil_div(W_B, P);
+  return w >= c ? (P * (w - c)) / W_B + 1 : 0;
+}
+
 /* Eq. 3: blocks allowed by the wave slots of one CU, including the block-slot
  * limit B_mp (waived for one-wave blocks when the target says so). */
 static int64_t or_G_W(const oracle_arch *a, int64_t W_B) {
-  int64_t by_waves = a->max_waves_per_cu / W_B;
+  int64_t by_waves = or_blocks_on_partitions(a, a->max_waves_per_cu / a->simd_per_cu, W_B);
   int64_t by_slots = (W_B == 1 && a->single_wave_exempt) ? OR_INF_BLOCKS : a->max_blocks_per_cu;
   return or_min(by_slots, by_waves);
 }
 
 /* Eq. 4, plain reading: waves that fit one partition's register file, capped
- * by its wave slots, summed over partitions, then whole blocks. */
+ * by its wave slots, then whole blocks over the partitions. */
 static int64_t or_G_R(const oracle_arch *a, int64_t R, int64_t W_B) {
   if (R == 0) return OR_INF_BLOCKS;           /* no register demand: not limiting */
   if (R > a->max_vgprs_per_thread) return 0;  /* beyond the per-thread maximum  */
   int64_t per_wave = or_round_up(R, a->vgpr_granule);
   int64_t slots = a->max_waves_per_cu / a->simd_per_cu;
   int64_t waves_per_simd = or_min(slots, a->vgprs_per_simd_lane / per_wave);
-  return (a->simd_per_cu * waves_per_simd) / W_B;
+  return or_blocks_on_partitions(a, waves_per_simd, W_B);
 }
 
 /* Eq. 5 with a floor: blocks whose LDS allocations fit the per-CU pool. */

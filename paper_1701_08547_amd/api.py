@@ -612,8 +612,9 @@ class Plan:
                                   ctypes.byref(wb)))
         self.shape = (info_shape.tile, info_shape.items_per_lane, info_shape.waves_per_block)
         self.n_items, self.n_splits, self.workspace_bytes = ni.value, ns.value, wb.value
+        torch = _torch()
         if device is None:
-            device = seg.device if hasattr(seg, "device") and seg.device.type == "cuda" else "cuda"
+            device = seg.device if isinstance(seg, torch.Tensor) and seg.device.type == "cuda" else "cuda"
         self.table = Workspace(int(lib().sa_plan_device_bytes(self._h)), device)
         _check(lib().sa_plan_bind(self._h, self.table.ptr, self.table.nbytes, _stream(stream)))
         # the copy reads this plan's host memory: let it finish here, so that

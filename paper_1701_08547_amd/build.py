@@ -25,6 +25,21 @@ HIPCC_FLAGS = [
 ]
 
 
+# sources the planned scoring kernel is built from: counter figures taken on
+# other sources are not reported
+PLAIN_KERNEL_SOURCES = ("sa_internal.h", "sa_dev.h", "sa_eval.hip", "sa_plan.hip")
+
+
+def plain_kernel_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in PLAIN_KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if c and (os.path.sep not in c or os.path.exists(c)):

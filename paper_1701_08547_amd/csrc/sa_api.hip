@@ -125,8 +125,8 @@ int32_t pick_tile(int64_t n_evals) {
 // wave counts, each rounded to 16 bytes.
 void set_lds_layout(sa::EvalLaunch &L) {
   const int32_t tab = (L.arch.nr + 2) * (L.arch.nw + 2);
-  L.tab_wtot_off = (tab + 15) & ~15;
-  L.dyn_lds_bytes = L.tab_wtot_off + (((L.arch.nr + 2) + 15) & ~15);
+  L.tab_wsimd_off = (tab + 15) & ~15;
+  L.dyn_lds_bytes = L.tab_wsimd_off + (((L.arch.nr + 2) + 15) & ~15);
 }
 
 bool all16(std::initializer_list<const void *> ps) {
@@ -138,6 +138,18 @@ bool all16(std::initializer_list<const void *> ps) {
 size_t frag_bytes(int64_t n_evals, int32_t tile, int32_t k) {
   const int64_t tiles = ceil_div(n_evals, tile);
   return (size_t)(2 * tiles * (int64_t)k * (int64_t)sizeof(uint64_t));
+}
+
+// Tile sa_score picks for the plain or the corrected pass.
+int32_t score_tile(int64_t n_evals, bool corrected) {
+  // the corrected pass does ~100x the work per evaluation: smallest tiles
+  return corrected ? (g_tile > 0 ? g_tile : sa::kTileMin) : pick_tile(n_evals);
+}
+
+// Workspace bytes one sa_score call uses (its fragment slots).
+size_t score_workspace_need(int64_t n_evals, int32_t k, bool corrected) {
+  if (n_evals <= 0 || k <= 0) return 0;
+  return frag_bytes(n_evals, score_tile(n_evals, corrected), k);
 }
 
 // Point the launch at its workspace: the fragment slots.
@@ -224,7 +236,7 @@ sa_status sa_arch_gfx950(sa_arch *out) {
   out->vgpr_granule = 8;
   out->max_vgprs_per_thread = 512;
   out->lds_per_cu = 163840;
-  out->lds_granule = 512;
+  out->lds_granule = 1280;
   out->max_lds_per_block = 163840;
   out->w_sat = 32;
   out->max_unroll = 64;
@@ -333,8 +345,7 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   L.topk_idx = topk_idx;
   L.topk_val = topk_val;
   L.k = topk ? k : 0;
-  // the corrected pass does ~100x the work per evaluation: smallest tiles
-  L.tile = mlp ? (g_tile > 0 ? g_tile : sa::kTileMin) : pick_tile(n_evals);
+  L.tile = score_tile(n_evals, mlp != nullptr);
   L.n_tiles = ceil_div(n_evals, L.tile);
   L.need_score = (score || topk) ? 1 : 0;
   L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves, score}) ? 1 : 0;

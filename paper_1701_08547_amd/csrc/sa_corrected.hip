@@ -5,10 +5,13 @@
 //
 // Work decomposition as the tile path of the plain pass (wave-tiles of
 // `tile` evaluations, pieces per overlapped segment, fragments merged by
-// sa_merge_kernel), with a persistent grid: each workgroup stages the
-// network's weights in LDS once and its waves stride over the wave-tiles.
-// A wave evaluates 64 configurations at a time (one per lane), writes their
-// normalised inputs to its LDS block and runs the forward pass on them.
+// sa_merge_kernel), with a persistent grid: each workgroup of sixteen waves
+// (one per CU: four per SIMD, at most 128 registers each) stages the
+// network's weights and the GELU pieces in LDS once, and its waves stride
+// over the wave-tiles independently.  A wave evaluates 64 configurations at a
+// time (one per lane), writes their normalised inputs to its LDS block and
+// runs the forward pass on them; its top-k candidates wait in a 256-key LDS
+// buffer.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -18,7 +21,8 @@
 namespace sa {
 namespace {
 
-constexpr int kCorrWaves = 8;
+constexpr int kCorrWaves = 16;
+constexpr int kCorrCap = 256;  // candidate keys per wave: k <= 64 plus one batch of 64, with room to spare
 
 template <bool HAS_GRID>
 __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunch L, MlpDev M) {
@@ -27,8 +31,8 @@ __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunc
   __shared__ uint32_t tab_mwb[kMaxWB + 2];
   __shared__ uint8_t tab_blim[kMaxWB + 2];
   __shared__ MlpLdsT s;
-  __shared__ WaveLds wl[kCorrWaves];
-  __shared__ __align__(16) uint16_t X[kCorrWaves][64 * kLdXT];
+  __shared__ WaveLdsT<kCorrCap> wl[kCorrWaves];
+  __shared__ __align__(16) uint16_t X[kCorrWaves][64 * kLdXin];
 
   const KArch &A = L.arch;
   const int tid = threadIdx.x;
@@ -38,7 +42,7 @@ __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunc
   load_weights_t(M, s, tid, 64 * kCorrWaves);
   __syncthreads();
   const Tables tb{dyn_lds, tab_rcap};
-  const uint8_t *tab_wtot = dyn_lds + L.tab_wtot_off;
+  const uint8_t *tab_wsimd = dyn_lds + L.tab_wsimd_off;
   const int64_t *seg = L.cfg.seg;
   const int64_t n_evals = L.n_evals;
   const int k = L.k;
@@ -64,24 +68,28 @@ __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunc
       float f[kMF];
       variant_features(f, L.var.n_fp[v], L.var.n_int[v], L.var.n_ld[v], L.var.n_st[v], L.var.n_br[v],
                        L.var.n_bar[v], L.var.n_reg ? L.var.n_reg[v] : 0, L.var.lds[v], L.var.div[v]);
+      // inputs 0..7 are the variant's: one packed slice for the whole piece
+      uint32_t xv0[4];
+      pack_inputs<4>(s, f, 0, xv0);
+      const u32x4_t xv = {xv0[0], xv0[1], xv0[2], xv0[3]};
       sel.count = 0;
       sel.theta = kThetaInit;
 
       for (int64_t base = e; base < pe; base += 64) {
-        if (topk) make_room(sel, 64, k, lane);
+        if (topk) make_room<kCorrCap>(sel, 64, k, lane);
         const int64_t row = base + lane;
         const bool in = row < pe;
         const int32_t T = in ? L.cfg.block[row] : 1;
         const int32_t U = in ? L.cfg.unroll[row] : 1;
         const int32_t R = in ? L.cfg.regs[row] : 0;
         const int32_t G = (HAS_GRID && in) ? L.cfg.grid[row] : 1;
-        const Terms t = eval_terms<HAS_GRID>(A, tb, tab_wtot, tab_mwb, tab_blim, pc, T, U, R, G, in);
+        const Terms t = eval_terms<HAS_GRID>(A, tb, tab_wsimd, tab_mwb, tab_blim, pc, T, U, R, G, in);
         if (L.occ && in) L.occ[row] = t.W;
         const bool legal = t.B > 0;
         config_features(f, T, U, R, G, HAS_GRID, A.n_cu, t.WB, t.gw, t.gr, t.gs, t.B, t.W, t.Ed, t.F, t.sc);
-        put_x(s, Xw, lane, f, !legal);
+        put_x_cfg(s, Xw, lane, f, !legal);
         wave_lds_sync();
-        const float delta = mlp_rows(s, Xw, lane);
+        const float delta = mlp_rows<true>(s, Xw, lane, xv);
         wave_lds_sync();
         const float z = legal ? f[22] + delta : __builtin_huge_valf();
         if (L.score && in) L.score[row] = z;
@@ -89,12 +97,12 @@ __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunc
           const uint32_t kk = order_key(z);
           const bool cand[1] = {legal && (z < __builtin_huge_valf()) && kk <= sel.theta};
           const uint64_t key[1] = {((uint64_t)kk << 32) | (uint32_t)(row - s0)};
-          offer<1>(sel, cand, key);
+          offer<1, kCorrCap>(sel, cand, key);
         }
       }
 
       if (topk) {
-        const uint64_t mine = select_k(sel, k, lane);
+        const uint64_t mine = select_k<kCorrCap>(sel, k, lane);
         if (e == s0 && pe == s1) {
           write_final(mine, k, lane, v, L.topk_idx, L.topk_val, nullptr, s0);
         } else {

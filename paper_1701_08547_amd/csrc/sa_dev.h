@@ -126,7 +126,7 @@ __device__ __forceinline__ int32_t udiv_up(int32_t a, int32_t b, float r) {
 // ---------------------------------------------------------------- selection
 
 struct Selector {
-  uint64_t *buf;   // this wave's candidate buffer (kCandCap keys, LDS)
+  uint64_t *buf;   // this wave's candidate buffer (CAP keys, LDS)
   uint32_t count;  // keys in buf (uniform)
   uint32_t theta;  // order key of the current k-th best score (uniform)
 };
@@ -140,21 +140,32 @@ __device__ __forceinline__ void cas64(uint64_t &a, uint64_t &b) {
 // Reduce buf[0, count) to its k smallest keys: afterwards lane r < found holds
 // the r-th smallest (kKeyNone elsewhere), buf[0, found) holds them too and
 // theta is the k-th smallest score when k keys exist.  Each lane sorts its
-// eight keys (Batcher's odd-even merge network); each of the k rounds takes
-// the minimum of the lane heads and the owner pops its head.
+// CAP / 64 keys (Batcher's odd-even merge network for 8, its first stages for
+// 4 and 2); each of the k rounds takes the minimum of the lane heads and the
+// owner pops its head.
+template <int CAP = kCandCap>
 __device__ uint64_t select_k(Selector &s, int k, int lane) {
-  static_assert(kCandCap == 8 * 64, "select_k holds eight keys per lane");
+  constexpr int PER = CAP / 64;
+  static_assert(PER == 2 || PER == 4 || PER == 8, "two, four or eight keys per lane");
   wave_lds_sync();
-  const uint32_t i0 = 8u * (uint32_t)lane;
-  uint64_t r[8];
+  const uint32_t i0 = (uint32_t)PER * (uint32_t)lane;
+  uint64_t r[PER];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) r[j] = i0 + j < s.count ? s.buf[i0 + j] : kKeyNone;
-  cas64(r[0], r[1]); cas64(r[2], r[3]); cas64(r[4], r[5]); cas64(r[6], r[7]);
-  cas64(r[0], r[2]); cas64(r[1], r[3]); cas64(r[4], r[6]); cas64(r[5], r[7]);
-  cas64(r[1], r[2]); cas64(r[5], r[6]);
-  cas64(r[0], r[4]); cas64(r[1], r[5]); cas64(r[2], r[6]); cas64(r[3], r[7]);
-  cas64(r[2], r[4]); cas64(r[3], r[5]);
-  cas64(r[1], r[2]); cas64(r[3], r[4]); cas64(r[5], r[6]);
+  for (int j = 0; j < PER; ++j) r[j] = i0 + j < s.count ? s.buf[i0 + j] : kKeyNone;
+  if constexpr (PER == 2) {
+    cas64(r[0], r[1]);
+  } else if constexpr (PER == 4) {
+    cas64(r[0], r[1]); cas64(r[2], r[3]);
+    cas64(r[0], r[2]); cas64(r[1], r[3]);
+    cas64(r[1], r[2]);
+  } else {
+    cas64(r[0], r[1]); cas64(r[2], r[3]); cas64(r[4], r[5]); cas64(r[6], r[7]);
+    cas64(r[0], r[2]); cas64(r[1], r[3]); cas64(r[4], r[6]); cas64(r[5], r[7]);
+    cas64(r[1], r[2]); cas64(r[5], r[6]);
+    cas64(r[0], r[4]); cas64(r[1], r[5]); cas64(r[2], r[6]); cas64(r[3], r[7]);
+    cas64(r[2], r[4]); cas64(r[3], r[5]);
+    cas64(r[1], r[2]); cas64(r[3], r[4]); cas64(r[5], r[6]);
+  }
   uint64_t mine = kKeyNone;
   int found = 0;
   uint32_t last_hi = 0;
@@ -175,8 +186,8 @@ __device__ uint64_t select_k(Selector &s, int k, int lane) {
     if (lane == q) mine = ((uint64_t)mh << 32) | ml;
     if (lane == owner) {
 #pragma unroll
-      for (int j = 0; j < 7; ++j) r[j] = r[j + 1];
-      r[7] = kKeyNone;
+      for (int j = 0; j < PER - 1; ++j) r[j] = r[j + 1];
+      r[PER - 1] = kKeyNone;
     }
     last_hi = mh;
     ++found;
@@ -191,15 +202,16 @@ __device__ uint64_t select_k(Selector &s, int k, int lane) {
 
 // Flush the buffer when fewer than `need` slots are free.  Called before a
 // batch is evaluated, where few registers are live.
+template <int CAP = kCandCap>
 __device__ __forceinline__ void make_room(Selector &s, uint32_t need, int k, int lane) {
-  if (s.count + need > (uint32_t)kCandCap) select_k(s, k, lane);
+  if (s.count + need > (uint32_t)CAP) select_k<CAP>(s, k, lane);
 }
 
 // Offer N rows of 64 keys (`cand[i]` marks the lanes offering key[i]) by
 // ballot + mbcnt compaction; make_room(64 N) must have run first.
-template <int N>
+template <int N, int CAP = kCandCap>
 __device__ __forceinline__ void offer(Selector &s, const bool (&cand)[N], const uint64_t (&key)[N]) {
-  static_assert(N * 64 + SA_K_MAX <= kCandCap, "buffer must hold k keys plus one batch");
+  static_assert(N * 64 + SA_K_MAX <= CAP, "buffer must hold k keys plus one batch");
   uint64_t bal[N];
   uint32_t c = 0;
 #pragma unroll
@@ -235,11 +247,13 @@ __device__ __forceinline__ void write_final(uint64_t mine, int k, int lane, int6
 
 // ---------------------------------------------------------------- evaluation
 
-struct __align__(16) WaveLds {
+template <int CAP>
+struct __align__(16) WaveLdsT {
   float a4[kMaxUnroll];  // (c_ctrl n_br) / U for U = 1 .. max_unroll
   float a5[kMaxWB + 2];  // c_sync (n_bar W_B)    for W_B = 1 .. nw (nw + 1: unused)
-  uint64_t cand[kCandCap];
+  uint64_t cand[CAP];
 };
+using WaveLds = WaveLdsT<kCandCap>;
 
 // Wave-uniform state of the piece being evaluated.
 struct Piece {
@@ -305,15 +319,16 @@ __device__ __forceinline__ void eval_cfg(const KArch &A, const Tables &tb, const
 // Every term of one configuration, for the learned correction's features:
 // the same binary32 sequence as eval_cfg (need_score set), plus W_B, the
 // bound B*, the separate wave-slot (G_W) and register (G_R) bounds, E' and
-// F.  `wtot`, `mwb` and `blim` are build_tables' per-granule wave counts,
-// ceil(2^16 / W_B) and block limits.  Illegal: B = W = 0, scores +inf.
+// F.  `wsimd`, `mwb` and `blim` are build_tables' per-granule waves per
+// partition, ceil(2^16 / W_B) and block limits.  Illegal: B = W = 0, scores
+// +inf.
 struct Terms {
   int32_t WB, gw, gr, gs, B, W;
   float Ed, F, sc;
 };
 
 template <bool HAS_GRID>
-__device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, const uint8_t *wtot, const uint32_t *mwb,
+__device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, const uint8_t *wsimd, const uint32_t *mwb,
                                             const uint8_t *blim, const Piece &pc, int32_t T, int32_t U, int32_t R,
                                             int32_t G, bool in) {
   Terms t;
@@ -329,10 +344,11 @@ __device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, co
   B = B < pc.gs ? B : pc.gs;
   B = ok ? B : 0;
   const int32_t W = __umul24(B, WB);
-  const int32_t gwv = (int32_t)(((uint32_t)A.max_waves * mwb[WB]) >> 16);
+  (void)mwb;
+  const int32_t gwv = blocks_on_partitions(A.max_waves / A.simd, WB, A.simd);
   t.WB = WB;
   t.gw = gwv < (int32_t)blim[WB] ? gwv : (int32_t)blim[WB];
-  t.gr = rg == 0 ? kUnlimited : (int32_t)(((uint32_t)wtot[rg] * mwb[WB]) >> 16);
+  t.gr = rg == 0 ? kUnlimited : blocks_on_partitions(wsimd[rg], WB, A.simd);
   t.gs = pc.gs;
   t.B = B;
   t.W = W;
@@ -398,20 +414,21 @@ __device__ void build_tables(const EvalLaunch &L, uint8_t *dyn_lds, float *tab_r
   const KArch &A = L.arch;
   const int row = A.nw + 2;
   uint8_t *tab_b = dyn_lds;
-  uint8_t *tab_wtot = dyn_lds + L.tab_wtot_off;
-  // waves the register file admits per register-granule count (Eq. 4 plain
-  // reading), all slots when no registers are named; granule count nr + 1
-  // stands for every illegal register count and admits none
+  uint8_t *tab_wsimd = dyn_lds + L.tab_wsimd_off;
+  // waves one partition's register file admits per register-granule count
+  // (Eq. 4 plain reading), capped by its wave slots; all slots when no
+  // registers are named; granule count nr + 1 stands for every illegal
+  // register count and admits none
   const int slots = A.max_waves / A.simd;
   for (int rg = tid; rg <= A.nr + 1; rg += nthreads) {
-    int wtot = A.max_waves;
+    int w = slots;
     if (rg > A.nr) {
-      wtot = 0;
+      w = 0;
     } else if (rg > 0) {
       const int per_simd = A.vgprs / (rg * A.vgpr_gran);
-      wtot = A.simd * (per_simd < slots ? per_simd : slots);
+      w = per_simd < slots ? per_simd : slots;
     }
-    tab_wtot[rg] = (uint8_t)wtot;
+    tab_wsimd[rg] = (uint8_t)w;
   }
   // Eq. 3 block slots, and ceil(2^16 / W_B) for exact small divisions; W_B =
   // nw + 1 stands for every illegal block size and admits no block
@@ -424,14 +441,15 @@ __device__ void build_tables(const EvalLaunch &L, uint8_t *dyn_lds, float *tab_r
   for (int i = tid; i <= A.max_waves; i += nthreads)
     tab_rcap[i] = i > 0 ? __uint_as_float(__float_as_uint(1.0f / (float)(A.n_cu * i)) + 3u) : 0.0f;
   __syncthreads();
-  // min(G_W, G_R) = min(B_lim, floor(wtot / W_B)): the register bound never
-  // exceeds floor(max_waves / W_B), the wave-slot part of Eq. 3
+  // min(G_W, G_R) = min(B_lim, blocks on min(slots, register waves) places
+  // per partition): the block count grows with the places, so the smaller
+  // of the two place counts decides
   const int n_tab = (A.nr + 2) * row;
   for (int i = tid; i < n_tab; i += nthreads) {
     const int rg = i / row, wb = i - rg * row;
     uint32_t b = 0;
     if (wb >= 1) {
-      b = ((uint32_t)tab_wtot[rg] * tab_mwb[wb]) >> 16;
+      b = (uint32_t)blocks_on_partitions(tab_wsimd[rg], wb, A.simd);
       b = b < tab_blim[wb] ? b : tab_blim[wb];
     }
     tab_b[i] = (uint8_t)b;
@@ -441,8 +459,8 @@ __device__ void build_tables(const EvalLaunch &L, uint8_t *dyn_lds, float *tab_r
 
 // The wave-uniform record of variant v (Eq. 5 bound, Eq. 6 per-variant sum,
 // divergence weight) and its per-U / per-W_B tables in this wave's LDS.
-template <Mode MODE>
-__device__ __forceinline__ void setup_piece(const EvalLaunch &L, Piece &pc, WaveLds &wl, int64_t v, int64_t s0,
+template <Mode MODE, class WL>
+__device__ __forceinline__ void setup_piece(const EvalLaunch &L, Piece &pc, WL &wl, int64_t v, int64_t s0,
                                             int lane) {
   const KArch &A = L.arch;
   pc.kept = 0;

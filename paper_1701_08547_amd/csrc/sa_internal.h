@@ -21,6 +21,17 @@ constexpr int32_t kTileMin = 1024;      // evaluations per wave-tile, smallest
 constexpr int32_t kTileMax = 65536;
 constexpr int32_t kTileDefault = 8192;
 
+// Blocks of WB waves admitted by `simd` partitions with w wave places each
+// (Eqs. 3-4 on a partitioned CU): up to `simd` waves a block puts each wave
+// on a different partition and the places pool; a larger block needs
+// c = ceil(WB / simd) free places on every partition and deals its waves
+// round-robin, which admits floor(simd (w - c) / WB) + 1 blocks.
+__host__ __device__ inline int32_t blocks_on_partitions(int32_t w, int32_t WB, int32_t simd) {
+  if (WB <= simd) return simd * w / WB;
+  const int32_t c = (WB + simd - 1) / simd;
+  return w >= c ? simd * (w - c) / WB + 1 : 0;
+}
+
 // Descriptor as the kernels read it: the public fields plus the sizes and
 // division constants the host derives from them once per call.
 struct KArch {
@@ -59,7 +70,7 @@ struct EvalLaunch {
   int64_t n_tiles;
   int32_t need_score;
   int32_t vec;            // every streamed column 16-byte aligned: vector loads
-  int32_t tab_wtot_off;   // dynamic LDS layout of the occupancy tables
+  int32_t tab_wsimd_off;  // dynamic LDS layout of the occupancy tables
   int32_t dyn_lds_bytes;
 };
 

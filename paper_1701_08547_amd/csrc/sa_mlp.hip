@@ -204,15 +204,15 @@ __global__ void sa_features_kernel(EvalLaunch L, float *feat) {
     float *f = feat + e * kF;
     const int32_t Tc = ok ? T : 1, Rc = ok ? R : 0, Uc = ok ? U : 1;
     const int32_t WB = (Tc + A.ws - 1) / A.ws;
-    const int32_t gw_waves = A.max_waves / WB;
+    const int32_t slots = A.max_waves / A.simd;
+    const int32_t gw_waves = blocks_on_partitions(slots, WB, A.simd);
     const int32_t blim = (WB == 1 && A.exempt) ? (1 << 30) : A.max_blocks;
     const int32_t gw = gw_waves < blim ? gw_waves : blim;
     int32_t gr = 1 << 30;
     if (Rc > 0) {
       const int32_t per = ((Rc + A.vgpr_gran - 1) / A.vgpr_gran) * A.vgpr_gran;
-      const int32_t slots = A.max_waves / A.simd;
       const int32_t wv = A.vgprs / per < slots ? A.vgprs / per : slots;
-      gr = A.simd * wv / WB;
+      gr = blocks_on_partitions(wv, WB, A.simd);
     }
     int32_t gs = 1 << 30;
     if (S > 0) gs = A.lds_cu / (((S + A.lds_gran - 1) / A.lds_gran) * A.lds_gran);
@@ -259,7 +259,7 @@ constexpr int kFwdWaves = 8;
 __global__ __launch_bounds__(64 * kFwdWaves) void sa_mlp_fwd_kernel(MlpDev M, const float *feat, int64_t n,
                                                                     float *delta) {
   __shared__ MlpLdsT s;
-  __shared__ __align__(16) uint16_t X[kFwdWaves][64 * kLdXT];
+  __shared__ __align__(16) uint16_t X[kFwdWaves][64 * kLdXin];
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
   load_weights_t(M, s, tid, 64 * kFwdWaves);
   __syncthreads();
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void sa_mlp_fwd_kernel(MlpDev M, co
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const float d = mlp_rows(s, X[w], lane);
+    const float d = mlp_rows<false>(s, X[w], lane, u32x4_t{0u, 0u, 0u, 0u});
     if (in) delta[row] = d;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();

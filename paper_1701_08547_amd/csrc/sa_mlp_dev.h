@@ -33,7 +33,6 @@ constexpr int kMK = 32;           // padded input width
 constexpr int kMF = 24;           // features
 constexpr int kLdW1 = kMK + 8;    // LDS row strides in bf16 elements (16-byte padding)
 constexpr int kLdW2 = kMH + 8;
-constexpr int kLdXT = kMK + 8;
 
 // Two binary32 values rounded to bfloat16 (nearest, ties to even), packed
 // low half first.
@@ -72,35 +71,45 @@ __device__ __forceinline__ float gelu_grad(float a) {
   return fmaf(a * e, 0.39894228f, phi_cdf);
 }
 
-// Inference GELU from an LDS table of the normal CDF: Phi sampled at
-// a_i = -8 + i / 32 (i = 0..512, exact erfc at table build), linearly
-// interpolated; a Phi(a) outside [-8, 8] is relu(a) to within 1e-14.  The
-// interpolation error of Phi is at most h^2 / 8 max|Phi''| = 3.0e-5 (h = 1/32),
-// far below the bfloat16 rounding that follows.
-constexpr int kGeluN = 512;
+// Inference GELU from an LDS table of linear pieces.  The forward pass works
+// on the scaled pre-activation t = 64 a + 512: the weights of the first two
+// layers are staged multiplied by 64 (exact in bfloat16) and their biases as
+// 64 b + 512, so the matrix cores deliver t directly.  On [i, i + 1) the
+// table holds the chord of GELU between a_i = (i - 512) / 64 and a_i+1 as
+// GELU ~ g0_i + t g1_i, so one multiply-add gives the value: the chord's
+// error is at most h^2 / 8 max|GELU''| = 2.4e-5 (h = 1/64, GELU'' = phi(a)
+// (2 - a^2) peaks at 2 phi(0)), well below the bfloat16 rounding that
+// follows.  Piece 0 (a < -8 + 1/64) is zero and piece 1023 (a >= 8 - 1/64) is
+// the identity a = (t - 512) / 64; an index clamped to [0, 1023] then also
+// covers every t outside [0, 1024): GELU(a) differs from 0 below a = -8 and
+// from a above a = 8 by less than 1e-14.
+constexpr int kGeluN = 1024;
+constexpr float kTScale = 64.0f;
+constexpr float kTOrigin = 512.0f;
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ float phi_exact(float x) { return 0.5f * erfcf(-x * 0.70710678118654752f); }
+__device__ __forceinline__ double gelu_exact(double a) { return 0.5 * a * erfc(-a * 0.70710678118654752440); }
 
-// GELU of N values in place.  All table positions are computed first and all
-// reads issued before the first interpolation, so that the reads' latency
-// overlaps instead of being paid once per value.  For t in [0, 512) the
-// fractional part t - floor(t) is exact.
+// (g0, g1) of piece i, from the binary64 GELU at its ends.
+__device__ __forceinline__ f32x2_t gelu_piece(int i) {
+  if (i <= 0) return f32x2_t{0.0f, 0.0f};
+  if (i >= kGeluN - 1) return f32x2_t{-kTOrigin / kTScale, 1.0f / kTScale};
+  const double a0 = (double)(i - 512) / 64.0, a1 = (double)(i + 1 - 512) / 64.0;
+  const double y0 = gelu_exact(a0), y1 = gelu_exact(a1);
+  const double g1 = y1 - y0;
+  return f32x2_t{(float)(y0 - (double)i * g1), (float)g1};
+}
+
+// GELU of N scaled pre-activations in place.  All table positions are
+// computed and all reads issued before the first multiply-add, so that the
+// reads' latency overlaps.
 template <int N>
-__device__ __forceinline__ void gelu_tab_n(float (&a)[N], const f32x2_t *tab) {
-  int idx[N];
-  float fr[N];
+__device__ __forceinline__ void gelu_t_n(float (&t)[N], const f32x2_t *tab) {
+  f32x2_t c[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const float t = __builtin_amdgcn_fmed3f(fmaf(a[i], 32.0f, 256.0f), 0.0f, 511.99997f);
-    idx[i] = (int)t;
-    fr[i] = __builtin_amdgcn_fractf(t);
-  }
-  f32x2_t e[N];
+  for (int i = 0; i < N; ++i) c[i] = tab[(uint32_t)__builtin_amdgcn_fmed3f(t[i], 0.0f, (float)(kGeluN - 1))];
 #pragma unroll
-  for (int i = 0; i < N; ++i) e[i] = tab[idx[i]];
-#pragma unroll
-  for (int i = 0; i < N; ++i) a[i] = a[i] * fmaf(fr[i], e[i].y, e[i].x);
+  for (int i = 0; i < N; ++i) t[i] = fmaf(t[i], c[i].y, c[i].x);
 }
 
 // ---------------------------------------------------------------- features
@@ -145,12 +154,14 @@ __device__ __forceinline__ void config_features(float *f, int32_t T, int32_t U, 
 
 // ---------------------------------------------------------------- forward pass
 
+constexpr int kLdXin = kMF;  // input row stride (bf16): the 24 features, no padding
+
 struct __align__(16) MlpLdsT {
-  uint16_t W1[kMH * kLdW1];  // W1[h][k]
-  uint16_t W2[kMH * kLdW2];  // W2[o][.], columns permuted per 32-wide chunk (see w2_column)
+  uint16_t W1[kMH * kLdW1];  // 64 W1[h][k]
+  uint16_t W2[kMH * kLdW2];  // 64 W2[o][.], columns permuted per 32-wide chunk (see w2_column)
   uint16_t w3p[kMH];         // w3 in the same permuted order
-  float b1[kMH], b2[kMH];
-  f32x2_t phi[kGeluN + 1];   // (Phi(a_i), Phi(a_i+1) - Phi(a_i))
+  float b1[kMH], b2[kMH];    // 64 b + 512
+  f32x2_t gelu[kGeluN];      // pieces (g0, g1)
   float mean[kMF], inv_std[kMF];
   float b3;
 };
@@ -163,45 +174,62 @@ __device__ __forceinline__ int w2_column(int p) {
   return 32 * c + (j < 4 ? 4 * q + j : 12 + 4 * q + j);
 }
 
+// bfloat16 bits times 64 (exact: only the exponent changes; zero stays zero).
+__device__ __forceinline__ uint16_t bf16_x64(uint16_t b) {
+  const float x = __builtin_bit_cast(float, (uint32_t)b << 16) * kTScale;
+  return (uint16_t)(__builtin_bit_cast(uint32_t, x) >> 16);
+}
+
 __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthreads) {
-  for (int i = tid; i < kMH * kMK; i += nthreads) s.W1[(i / kMK) * kLdW1 + (i % kMK)] = M.W1[i];
+  for (int i = tid; i < kMH * kMK; i += nthreads) s.W1[(i / kMK) * kLdW1 + (i % kMK)] = bf16_x64(M.W1[i]);
   for (int i = tid; i < kMH * kMH; i += nthreads) {
     const int o = i / kMH, p = i % kMH;
-    s.W2[o * kLdW2 + p] = M.W2[o * kMH + w2_column(p)];
+    s.W2[o * kLdW2 + p] = bf16_x64(M.W2[o * kMH + w2_column(p)]);
   }
   for (int i = tid; i < kMH; i += nthreads) {
-    s.b1[i] = M.b1[i];
-    s.b2[i] = M.b2[i];
+    s.b1[i] = fmaf(M.b1[i], kTScale, kTOrigin);
+    s.b2[i] = fmaf(M.b2[i], kTScale, kTOrigin);
     s.w3p[i] = M.w3[w2_column(i)];
   }
   for (int i = tid; i < kMF; i += nthreads) {
     s.mean[i] = M.mean[i];
     s.inv_std[i] = M.inv_std[i];
   }
-  for (int i = tid; i <= kGeluN; i += nthreads) {
-    const float p0 = phi_exact(-8.0f + (float)i / 32.0f);
-    const float p1 = i < kGeluN ? phi_exact(-8.0f + (float)(i + 1) / 32.0f) : p0;
-    s.phi[i] = f32x2_t{p0, p1 - p0};
-  }
+  for (int i = tid; i < kGeluN; i += nthreads) s.gelu[i] = gelu_piece(i);
   if (tid == 0) s.b3 = M.b3[0];
 }
 
-// Row `row` of the wave's input block: bf16((f - mean) * inv_std) for the 24
-// features, then eight zeros.  `zero` writes an all-zero row (rows that do
-// not exist or are illegal).
+// Features i0 .. i0 + 2 n - 1 as network inputs: bf16((f - mean) * inv_std),
+// packed in pairs.
+template <int N>
+__device__ __forceinline__ void pack_inputs(const MlpLdsT &s, const float *f, int i0, uint32_t *p) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int a = i0 + 2 * i;
+    p[i] = pack_bf16((f[a] - s.mean[a]) * s.inv_std[a], (f[a + 1] - s.mean[a + 1]) * s.inv_std[a + 1]);
+  }
+}
+
+// Row `row` of the wave's input block: the 24 inputs (three 16-byte slices).
+// `zero` writes an all-zero row (rows that do not exist).
 __device__ __forceinline__ void put_x(const MlpLdsT &s, uint16_t *X, int row, const float *f, bool zero) {
   uint32_t p[12];
+  pack_inputs<12>(s, f, 0, p);
+  u32x4_t *dst = (u32x4_t *)(X + row * kLdXin);
 #pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    const float lo = (f[2 * i] - s.mean[2 * i]) * s.inv_std[2 * i];
-    const float hi = (f[2 * i + 1] - s.mean[2 * i + 1]) * s.inv_std[2 * i + 1];
-    p[i] = zero ? 0u : pack_bf16(lo, hi);
-  }
-  u32x4_t *dst = (u32x4_t *)(X + row * kLdXT);
-  dst[0] = u32x4_t{p[0], p[1], p[2], p[3]};
-  dst[1] = u32x4_t{p[4], p[5], p[6], p[7]};
-  dst[2] = u32x4_t{p[8], p[9], p[10], p[11]};
-  dst[3] = u32x4_t{0u, 0u, 0u, 0u};
+  for (int j = 0; j < 3; ++j)
+    dst[j] = zero ? u32x4_t{0u, 0u, 0u, 0u} : u32x4_t{p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]};
+}
+
+// The same row when inputs 0..7 (slice 0) are the variant's and shared by
+// every row of the block: only slices 1 and 2 (inputs 8..23) are written.
+__device__ __forceinline__ void put_x_cfg(const MlpLdsT &s, uint16_t *X, int row, const float *f, bool zero) {
+  uint32_t p[8];
+  pack_inputs<8>(s, f, 8, p);
+  u32x4_t *dst = (u32x4_t *)(X + row * kLdXin);
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    dst[j + 1] = zero ? u32x4_t{0u, 0u, 0u, 0u} : u32x4_t{p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]};
 }
 
 __device__ __forceinline__ f32x4_t mfma32(u32x4_t a, u32x4_t b, f32x4_t c) {
@@ -209,85 +237,91 @@ __device__ __forceinline__ f32x4_t mfma32(u32x4_t a, u32x4_t b, f32x4_t c) {
                                                  0, 0, 0);
 }
 
+// Eight values of an MFMA output pair (two row tiles) through GELU, packed
+// to bfloat16 in pairs: out[i][0..1] for row tile i.
+__device__ __forceinline__ void gelu_pack(const f32x4_t (&d)[2], const f32x2_t *tab, uint32_t (&out)[2][2]) {
+  float v[8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[4 * i + j] = d[i][j];
+  gelu_t_n<8>(v, tab);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    out[i][0] = pack_bf16(v[4 * i], v[4 * i + 1]);
+    out[i][1] = pack_bf16(v[4 * i + 2], v[4 * i + 3]);
+  }
+}
+
 // Delta of row `lane` of the wave's 64-row input block X (put_x rows; the
 // caller orders the writes before this call).  h1 = bf16(GELU(W1 x + b1)),
 // h2 = bf16(GELU(W2 h1 + b2)), Delta = w3 . h2 + b3, all three layers on the
-// matrix cores with fp32 accumulation.  A layer's output tiles (hidden units
-// 16 t + 4 q + j of row r at lane 16 q + r) are, packed in pairs, the B
-// operands of the next layer once its weight columns are permuted as in
-// w2_column.  The third layer multiplies every A row by w3, so row 4 q of its
-// result, which lane 16 q + r holds, is the sum for row r of the row tile.
-__device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, int lane) {
+// matrix cores with fp32 accumulation, in two passes of 32 rows (row tiles
+// 2 p and 2 p + 1) so that one pass's first hidden layer fits in 32
+// registers.  A layer's output tiles (hidden units 16 t + 4 q + j of row r
+// at lane 16 q + r) are, packed in pairs, the B operands of the next layer
+// once its weight columns are permuted as in w2_column.  Input slice q = 3
+// (features 24..31) is zero.  The third layer multiplies every A row by w3,
+// so row 4 q of its result, which lane 16 q + r holds, is the sum for row r
+// of the row tile.  SHARED: slice 0 of every row is `xv` (put_x_cfg rows),
+// not read from X.
+template <bool SHARED>
+__device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, int lane, u32x4_t xv) {
   const int r = lane & 15, q = lane >> 4;
-  u32x4_t xb[4];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt) xb[rt] = *(const u32x4_t *)(X + (16 * rt + r) * kLdXT + 8 * q);
-  // layer 1: h-tile t, row tile rt -> 4 packed bf16 (two dwords)
-  uint32_t h1[8][4][2];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const u32x4_t a = *(const u32x4_t *)(s.W1 + (16 * t + r) * kLdW1 + 8 * q);
-    const f32x4_t bias = *(const f32x4_t *)(s.b1 + 16 * t + 4 * q);
-    float v[16];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const f32x4_t d = mfma32(a, xb[rt], bias);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[4 * rt + j] = d[j];
-    }
-    gelu_tab_n<16>(v, s.phi);
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      h1[t][rt][0] = pack_bf16(v[4 * rt], v[4 * rt + 1]);
-      h1[t][rt][1] = pack_bf16(v[4 * rt + 2], v[4 * rt + 3]);
-    }
-  }
-  // layers 2 and 3, one 32-unit chunk of the second hidden layer at a time
-  f32x4_t acc3[4];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt) acc3[rt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  const int qx = q == 0 ? (SHARED ? 1 : 0) : (q < 3 ? q : 2);
+  float delta = 0.0f;
 #pragma unroll 1
-  for (int c3 = 0; c3 < 4; ++c3) {
-    uint32_t h2[2][4][2];
+  for (int p = 0; p < 2; ++p) {
+    u32x4_t xb[2];
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int ot = 2 * c3 + half;
-      const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
-      f32x4_t acc[4] = {bias, bias, bias, bias};
+    for (int i = 0; i < 2; ++i) {
+      const u32x4_t x = *(const u32x4_t *)(X + (16 * (2 * p + i) + r) * kLdXin + 8 * qx);
+      xb[i] = q == 3 ? u32x4_t{0u, 0u, 0u, 0u} : ((SHARED && q == 0) ? xv : x);
+    }
+    // layer 1: hidden tile t -> two row tiles x 4 packed bf16 (two dwords)
+    uint32_t h1[8][2][2];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
+    for (int t = 0; t < 8; ++t) {
+      const u32x4_t a = *(const u32x4_t *)(s.W1 + (16 * t + r) * kLdW1 + 8 * q);
+      const f32x4_t bias = *(const f32x4_t *)(s.b1 + 16 * t + 4 * q);
+      const f32x4_t d[2] = {mfma32(a, xb[0], bias), mfma32(a, xb[1], bias)};
+      gelu_pack(d, s.gelu, h1[t]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // layers 2 and 3, one 32-unit chunk of the second hidden layer at a time
+    f32x4_t acc3[2] = {f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}, f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll 1
+    for (int c3 = 0; c3 < 4; ++c3) {
+      uint32_t h2[2][2][2];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const u32x4_t b = {h1[2 * c][rt][0], h1[2 * c][rt][1], h1[2 * c + 1][rt][0], h1[2 * c + 1][rt][1]};
-          acc[rt] = mfma32(a, b, acc[rt]);
+      for (int half = 0; half < 2; ++half) {
+        const int ot = 2 * c3 + half;
+        const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
+        f32x4_t acc[2] = {bias, bias};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const u32x4_t b = {h1[2 * c][i][0], h1[2 * c][i][1], h1[2 * c + 1][i][0], h1[2 * c + 1][i][1]};
+            acc[i] = mfma32(a, b, acc[i]);
+          }
         }
+        gelu_pack(acc, s.gelu, h2[half]);
+        __builtin_amdgcn_sched_barrier(0);
       }
-      float v[16];
+      const u32x4_t a3 = *(const u32x4_t *)(s.w3p + 32 * c3 + 8 * q);
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[4 * rt + j] = acc[rt][j];
-      gelu_tab_n<16>(v, s.phi);
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        h2[half][rt][0] = pack_bf16(v[4 * rt], v[4 * rt + 1]);
-        h2[half][rt][1] = pack_bf16(v[4 * rt + 2], v[4 * rt + 3]);
+      for (int i = 0; i < 2; ++i) {
+        const u32x4_t b = {h2[0][i][0], h2[0][i][1], h2[1][i][0], h2[1][i][1]};
+        acc3[i] = mfma32(a3, b, acc3[i]);
       }
     }
-    const u32x4_t a3 = *(const u32x4_t *)(s.w3p + 32 * c3 + 8 * q);
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const u32x4_t b = {h2[0][rt][0], h2[0][rt][1], h2[1][rt][0], h2[1][rt][1]};
-      acc3[rt] = mfma32(a3, b, acc3[rt]);
-    }
+    // lane l = 16 q + r owns row l, which is row r of row tile q
+    delta = q == 2 * p ? acc3[0][0] : delta;
+    delta = q == 2 * p + 1 ? acc3[1][0] : delta;
   }
-  // lane l = 16 q + r owns row l, which is row r of row tile q
-  float d = acc3[0][0];
-  d = q == 1 ? acc3[1][0] : d;
-  d = q == 2 ? acc3[2][0] : d;
-  d = q == 3 ? acc3[3][0] : d;
-  return d + s.b3;
+  return delta + s.b3;
 }
 
 }  // namespace

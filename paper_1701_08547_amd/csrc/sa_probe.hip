@@ -76,10 +76,12 @@ struct ProbeEntry {
 
 #define SA_PROBE(LB, R) {LB, R, sa_residency_kernel<LB, R>}
 const ProbeEntry kProbes[] = {
-    SA_PROBE(64, 16),   SA_PROBE(64, 24),   SA_PROBE(64, 64),   SA_PROBE(64, 72),  SA_PROBE(64, 80),
-    SA_PROBE(64, 128),  SA_PROBE(64, 256),  SA_PROBE(64, 512),  SA_PROBE(128, 16), SA_PROBE(128, 64),
-    SA_PROBE(128, 256), SA_PROBE(192, 96),  SA_PROBE(256, 64),  SA_PROBE(256, 128), SA_PROBE(320, 168),
-    SA_PROBE(512, 80),  SA_PROBE(1024, 64), SA_PROBE(1024, 128),
+    SA_PROBE(64, 16),   SA_PROBE(64, 24),   SA_PROBE(64, 64),   SA_PROBE(64, 72),   SA_PROBE(64, 80),
+    SA_PROBE(64, 128),  SA_PROBE(64, 256),  SA_PROBE(64, 512),  SA_PROBE(128, 16),  SA_PROBE(128, 64),
+    SA_PROBE(128, 256), SA_PROBE(192, 16),  SA_PROBE(192, 96),  SA_PROBE(192, 168), SA_PROBE(256, 64),
+    SA_PROBE(256, 128), SA_PROBE(320, 16),  SA_PROBE(320, 96),  SA_PROBE(320, 168), SA_PROBE(384, 16),
+    SA_PROBE(384, 128), SA_PROBE(448, 16),  SA_PROBE(512, 80),  SA_PROBE(576, 16),  SA_PROBE(640, 16),
+    SA_PROBE(768, 16),  SA_PROBE(960, 16),  SA_PROBE(1024, 64), SA_PROBE(1024, 128),
 };
 #undef SA_PROBE
 

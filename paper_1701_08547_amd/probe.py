@@ -15,8 +15,9 @@ import ctypes
 import numpy as np
 
 # (block rounded up to 64, vgprs) pairs the library has probe kernels for
-PROBES = {64: (16, 24, 64, 72, 80, 128, 256, 512), 128: (16, 64, 256), 192: (96,), 256: (64, 128), 320: (168,),
-          512: (80,), 1024: (64, 128)}
+PROBES = {64: (16, 24, 64, 72, 80, 128, 256, 512), 128: (16, 64, 256), 192: (16, 96, 168), 256: (64, 128),
+          320: (16, 96, 168), 384: (16, 128), 448: (16,), 512: (80,), 576: (16,), 640: (16,), 768: (16,), 960: (16,),
+          1024: (64, 128)}
 
 
 def cu_key(hw_id: np.ndarray, xcc_id: np.ndarray) -> np.ndarray:

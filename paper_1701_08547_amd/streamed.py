@@ -169,7 +169,7 @@ def main(argv=None):
            "generate_ms": t_gen, "plain_ms": t_plain, "corrected_ms": t_corr, "graph_both_ms": t_graph,
            "plain_configs_per_s": n / (t_plain * 1e-3), "corrected_configs_per_s": n / (t_corr * 1e-3),
            "plain_read_GBps": 16 * n / (t_plain * 1e-3) / 1e9,
-           "corrected_mfma_TFLOPs": 41216 * n / (t_corr * 1e-3) / 1e12,
+           "corrected_mfma_TFLOPs": 39168 * n / (t_corr * 1e-3) / 1e12,
            "pipeline_configs_per_s": n / (t_graph * 1e-3),
            "correction_regret": {k2: rep["all"][k2] for k2 in ("regret_plain", "regret_corrected", "spearman_plain",
                                                                "spearman_corrected")},

@@ -192,8 +192,9 @@ def test_adam_over_consecutive_steps():
     fed with the gradient the step returned.  Catches beta1/beta2 mixed up and
     a bias correction that does not follow t."""
     arch = oracle.arch_cdna4()
-    b = feature_batch(71, [2200])
+    b = feature_batch(71, [9000])
     f = oracle_features(b, arch)[legal_mask(b, arch)][:2048]
+    assert f.shape[0] == 2048
     p, mean, inv, s = surrogate(13, f)
     rng = np.random.default_rng(5)
     target = (0.4 * np.tanh(f[:, 22] - f[:, 22].mean()) + 0.05 * rng.standard_normal(f.shape[0])).astype(np.float32)
@@ -316,3 +317,26 @@ def test_pairwise_training_orders_groups():
     rho_z = np.mean([mlp.spearman(z[i:i + 128], y[i:i + 128]) for i in range(0, 4096, 128)])
     say("pairwise training: loss", losses[0], "->", losses[-1], "spearman", rho_plain, "->", rho_z)
     assert rho_z > rho_plain + 0.05
+
+
+def test_training_and_inference_forward_agree():
+    """The training step's forward (exact-erf GELU by A&S 7.1.26, 16x16x16
+    MFMAs) and the inference forward (GELU chords from the LDS table,
+    16x16x32 MFMAs) compute the same network: with the inference Delta as
+    the target, the loss a training step reports is the mean squared gap
+    between the two, and its gradient for b3 is twice the mean gap.  Both
+    stay within the bf16 band the oracle comparisons claim."""
+    arch = oracle.arch_cdna4()
+    b = feature_batch(73, [9000])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:4096]
+    p, mean, inv, s = surrogate(17, f)
+    ft = torch.from_numpy(f).cuda()
+    d_inf = s.forward(ft)
+    torch.cuda.synchronize()
+    rms_delta = float(d_inf.pow(2).mean().sqrt().item())
+    mse_gap = float(s.train_step(ft, d_inf.clone(), lr=1e-30).item())
+    torch.cuda.synchronize()
+    mean_gap = float(s.grad[api.FLAT_B3].item()) / 2.0
+    say("train/infer gap: rms %.3g mean %.3g (rms Delta %.3g)" % (mse_gap ** 0.5, mean_gap, rms_delta))
+    assert mse_gap ** 0.5 <= 2 ** -9 * (1.0 + rms_delta)
+    assert abs(mean_gap) <= 2 ** -10 * (1.0 + rms_delta)

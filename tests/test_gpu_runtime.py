@@ -106,3 +106,32 @@ def test_stream_ceiling_moves_every_element(items, bpc, nt):
     c = [x.cpu().numpy() for x in cols]
     assert np.array_equal(outs[0].cpu().numpy(), (c[0].astype(np.int64) + c[1]).astype(np.uint32).view(np.int32))
     assert np.array_equal(outs[1].cpu().numpy(), c[2] ^ c[3])
+
+
+def test_instruction_costs_by_microbenchmark():
+    """sa_rt_cpi (Table II's quantity on this device, Sec. III-B): every
+    category of Eq. 6 gets a finite, positive cost; a cached load costs more
+    than an FP32 multiply-add, which costs at most one CU-cycle per 64
+    lanes (a SIMD issues at least 16 lanes per cycle); and the descriptor
+    built from the measured costs is one the library accepts."""
+    from paper_1701_08547_amd import calibration
+
+    meas = calibration.measure_cpi(reps=5)
+    print("cpi", {c: round(v[0], 5) for c, v in meas.items()}, flush=True)
+    for c in calibration.CATEGORIES:
+        cpi, ms = meas[c]
+        assert np.isfinite(cpi) and cpi > 0, c
+        assert np.isfinite(ms) and ms > 0, c
+    assert meas["mem"][0] > meas["fp"][0]
+    assert meas["fp"][0] <= 1.0 / 64
+    cal = calibration.calibrated_arch(api.arch_default(0), meas)
+    api.arch_validate(cal)
+    # the measured constants score a batch like the defaults do, only the weights change
+    from paper_1701_08547_amd import workloads
+    import oracle
+
+    b = workloads.custom_batch(5, [300, 77], with_grid=True, name="cpi")
+    var, cfg = api.device_batch(b)
+    out = api.score(cal, var, cfg, k=4)
+    ref = oracle.run(cal, b.variants, b.configs(), k=4)
+    assert np.array_equal(out["score"].cpu().numpy().view(np.uint32), ref["score32"].view(np.uint32))

@@ -216,7 +216,8 @@ def test_closed_form_matches_residency_simulator():
           384, 511, 512, 513]
     for name, a in [("cdna4", oracle.arch_cdna4())] + [(g, oracle.arch_paper(g)) for g in GPUS]:
         pool = a["lds_per_cu"]
-        Ss = [0, 1, 511, 512, 513, 5376, 6144, 8192, 20000, pool // 3, pool // 2, pool - 1, pool, pool + 1]
+        Ss = [0, 1, 511, 512, 513, 1280, 1281, 5376, 6144, 6400, 6401, 8192, 11520, 20000, pool // 3, pool // 2,
+              pool - 1, pool, pool + 1]
         for T in Ts:
             for R in Rs:
                 for S in Ss:
@@ -240,7 +241,8 @@ def test_occupancy_invariants():
         assert oracle.occupancy(a, T, R, min(163840, S + int(g.integers(1, 8192)))) <= W
         if B > 0:
             if S > 0:
-                assert B * (-(-S // 512) * 512) <= a["lds_per_cu"]
+                g_l = a["lds_granule"]
+                assert B * (-(-S // g_l) * g_l) <= a["lds_per_cu"]
             if R > 0:
                 wv = min(8, 512 // (-(-R // 8) * 8))
                 assert B * W_B <= 4 * wv
