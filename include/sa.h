@@ -253,6 +253,24 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
                    size_t workspace_bytes, void *stream);
 
 /*
+ * sa_score for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same pass, arguments and results as sa_score, without the workspace.  Its
+ * fragment slots live in a fixed array of SA_NOALLOC_SCRATCH_BYTES bytes of
+ * device memory that the library holds on each GPU it runs on until the
+ * process ends; the call allocates nothing.  A problem whose slots exceed
+ * that array (sa_workspace_bytes-style need for the tile the pass uses: 16 k
+ * bytes per 1,024 evaluations for the corrected pass, per 8,192 for the plain
+ * one) returns SA_ERR_WORKSPACE before any launch.  Every call on one GPU
+ * shares its array: calls that overlap in time on one GPU race (order them on
+ * one stream).  Errors as sa_score.
+ */
+#define SA_NOALLOC_SCRATCH_BYTES (4 << 20)
+sa_status sa_score_noalloc(const sa_arch *arch, const sa_variants *variants, const sa_configs *configs,
+                           int64_t n_variants, int64_t n_evals, float *score, int32_t *occ_waves, int32_t k,
+                           int32_t *topk_idx, float *topk_val, const sa_mlp *mlp, void *stream);
+
+/*
  * Segmented top-k over given keys: for each segment [seg[v], seg[v+1]) of
  * keys (float[n_evals]) the k smallest finite-or-negative-infinite keys
  * (NaN and +inf are excluded), ties by smaller local index; idx

@@ -42,7 +42,7 @@ EXPORTED = (
     "sa_rt_last_error", "sa_rt_grid", "sa_rt_trips", "sa_rt_buffer_floats", "sa_rt_measure", "sa_rt_cpi",
     "sa_rt_stream", "sa_rt_residency",
     "sa_suggest", "sa_score_suggested", "sa_headroom", "sa_gen_configs",
-    "sa_product_workspace_bytes", "sa_score_product",
+    "sa_product_workspace_bytes", "sa_score_product", "sa_score_noalloc",
 )
 MLP_PARAMS = 20865
 MLP_FLAT = 20992
@@ -116,6 +116,9 @@ def lib():
             L.sa_score.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp,
                                    P(SaMlp), vp, sz, vp]
             L.sa_score.restype = i32
+            L.sa_score_noalloc.argtypes = [P(SaArch), P(SaVariants), P(SaConfigs), i64, i64, vp, vp, i32, vp, vp,
+                                           P(SaMlp), vp]
+            L.sa_score_noalloc.restype = i32
             L.sa_topk.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp, sz, vp]
             L.sa_topk.restype = i32
             L.sa_set_tile.argtypes = [i32]

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa.so")
 SOURCES = ["sa_api.hip", "sa_eval.hip", "sa_plan.hip", "sa_mlp.hip", "sa_mlp_api.hip", "sa_corrected.hip",
-           "sa_runtime.hip", "sa_gen.hip", "sa_cpi.hip", "sa_product.hip", "sa_probe.hip"]
+           "sa_runtime.hip", "sa_gen.hip", "sa_cpi.hip", "sa_product.hip", "sa_probe.hip", "sa_noalloc.hip"]
 # gfx950 assembly of the measured kernel families, read by the static
 # feature extractor (same device flags as the library)
 RUNTIME_ASM = os.path.join(PKG, "sa_runtime_gfx950.s")
