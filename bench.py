@@ -61,6 +61,8 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 VALU_PEAK_LANE_OPS = 157.3e12 / 2
 # algorithmic dense work per evaluation: 24->128->128->1 (the K padding to 32 is not counted)
 MLP_FLOP_PER_EVAL = 2 * (24 * 128 + 128 * 128 + 128)
+# one training row: that forward, dL/dh1 = W2^T dL/da2, dW2, dW1 and dw3
+TRAIN_FLOP_PER_ROW = MLP_FLOP_PER_EVAL + 2 * (128 * 128 + 128 * 128 + 24 * 128 + 128)
 BYTES_PER_EVAL = 24
 K = 8
 def parse():
@@ -78,11 +80,12 @@ def parse():
                    help="only run a plain device copy of 256,000 KiB (counter calibration under rocprofv3)")
     p.add_argument("--corrected-steps", type=int, default=10,
                    help="timed launches of the fused corrected pass on the same workload (0: skip)")
-    p.add_argument("--regret-per-family", type=int, default=30,
+    p.add_argument("--regret-per-family", type=int, default=45,
                    help="instances per kernel family measured for the regret leg (0: skip)")
     p.add_argument("--product-steps", type=int, default=20,
                    help="timed launches of the same workload as a product space without rows (0: skip)")
     p.add_argument("--only-plain", action="store_true", help="the plain leg alone (profiling runs)")
+    p.add_argument("--no-stream-ceiling", action="store_true", help="skip the stream-ceiling sweep (profiling runs)")
     p.add_argument("--cpu-baseline-batches", action="store_true",
                    help="host only: the cpu_baseline leg (the CPU oracle) on every batch shape, one thread and all "
                         "threads (no GPU work)")
@@ -93,6 +96,8 @@ def parse():
     p.add_argument("--cold-steps", type=int, default=30, help="timed launches of the cold-cache leg (0: skip)")
     p.add_argument("--c2-steps", type=int, default=20, help="timed launches of the 10,000-variant leg (0: skip)")
     p.add_argument("--c4", type=int, default=1, help="run the 100,000-variant streamed leg (0: skip)")
+    p.add_argument("--train-epochs", type=int, default=2,
+                   help="timed epochs (256 steps of 4,096 rows each) of the training leg (0: skip)")
     return p.parse_args()
 
 
@@ -332,13 +337,16 @@ def main():
             line["corrected"] = corrected_leg(arch, var, cfg, n_var, n_evals, sur, args.corrected_steps)
         if args.product_steps > 0:
             line["product"] = product_leg(arch, var, n_var, n_evals, outs, args.product_steps)
-        line["stream_ceiling"] = stream_ceiling(cfg, n_evals, achieved)
+        if not args.no_stream_ceiling:
+            line["stream_ceiling"] = stream_ceiling(cfg, n_evals, achieved)
         if args.cold_steps > 0:
             line["cold"] = cold_leg(arch, var, cfg, plan, n_var, n_evals, args.cold_steps)
         if args.c2_steps > 0:
             line["c2"] = c2_leg(arch, args.c2_steps)
         if args.c4:
             line["c4"] = c4_leg(arch, sur)
+        if args.train_epochs > 0:
+            line["training"] = training_leg(args.train_epochs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -494,6 +502,52 @@ def c4_leg(arch, sur) -> dict:
             "seconds": time.perf_counter() - t0}
 
 
+def training_leg(epochs: int, n: int = 1 << 20, batch: int = 4096) -> dict:
+    """Training steps of the learned correction as the training loop runs
+    them: 2^20 synthetic rows (24 N(0, 1) features, N(0, 0.01) targets),
+    batches of 4,096, each epoch's 256 steps (one fused forward/backward
+    kernel and one Adam kernel each) captured in one HIP graph; the timed
+    region is `epochs` replays between HIP events on the replay stream."""
+    import numpy as np
+    import torch
+
+    from paper_1701_08547_amd import api, correction
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(170108547)
+    feat = torch.randn((n, 24), generator=g, device="cuda")
+    target = torch.randn(n, generator=g, device="cuda") * 0.1
+    sur = api.Surrogate(correction.init_params(0), np.zeros(24, np.float32), np.ones(24, np.float32))
+    sur.reserve(batch)
+    starts = list(range(0, n - batch + 1, batch))
+    sur.steps_dev.fill_(0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for b0 in starts:
+            sur.train_step(feat[b0:b0 + batch], target[b0:b0 + batch], lr=1e-3, device_counter=True)
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(epochs):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    steps = epochs * len(starts)
+    ms = e0.elapsed_time(e1) / steps
+    tflops = TRAIN_FLOP_PER_ROW * batch / (ms * 1e-3) / 1e12
+    loss = float(sur.grad[api.MLP_PARAMS].item())
+    return {"us_per_step": ms * 1e3, "rows_per_step": batch, "steps": steps, "rows_per_s": batch / (ms * 1e-3),
+            "kernels": "sa_train_kernel + sa_train_adam_kernel per step, one graph per epoch",
+            "flop_per_row": TRAIN_FLOP_PER_ROW, "TFLOPs": tflops, "frac_of_bf16_peak": tflops / MFMA_BF16_PEAK_TFLOPS,
+            "last_loss": loss, "device_steps": int(sur.steps_dev.item())}
+
+
 def stream_ceiling(cfg, n_evals: int, achieved: float) -> dict:
     """A pure stream of the plain pass's traffic (the four configuration
     columns read, two 4-byte columns written, no model arithmetic) over a
@@ -563,21 +617,28 @@ def product_leg(arch, var, n_var, n_evals, outs, steps: int) -> dict:
 
 def regret_leg(per_family: int):
     """Top-1 regret against measured runtimes: a small measured dataset of the
-    library's kernel families, the correction trained on 90 % of its
-    instances, plain and corrected keys compared on the rest."""
+    library's kernel families (the paper's timing protocol), the correction
+    trained on three quarters of each family's instances and evaluated on the
+    rest; the same with each family left out of training entirely; and the
+    model-guided search run live on the held-out instances (the full sweep and
+    the 8 survivors of each key timed again, wall clock compared)."""
     from paper_1701_08547_amd import correction, runtime_dataset
 
     t0 = time.perf_counter()
     data = runtime_dataset.build(per_family, seed=7)
-    sur, rep = correction.run(data, epochs=150, seed=7)
+    sur, rep = correction.run(data, epochs=150, seed=7, held_frac=0.25)
     a = rep["all"]
-    return sur, {"instances": int(data["instance"].max()) + 1, "held_out": a["instances"],
-                 "regret_plain": a["regret_plain"], "regret_corrected": a["regret_corrected"],
-                 "spearman_plain": a["spearman_plain"], "spearman_corrected": a["spearman_corrected"],
-                 "paper_pruned_fraction": a.get("pruned_fraction"),
-                 "regret_paper_pruned_plain": a.get("regret_pruned_plain"),
-                 "regret_paper_pruned_best": a.get("regret_pruned_best"),
-                 "seconds": time.perf_counter() - t0}
+    out = {"instances": int(data["instance"].max()) + 1, "held_out": a["instances"],
+           "regret_plain": a["regret_plain"], "regret_corrected": a["regret_corrected"],
+           "regret_diff_ci": a["regret_diff_ci"],
+           "spearman_plain": a["spearman_plain"], "spearman_corrected": a["spearman_corrected"],
+           "paper_pruned_fraction": a.get("pruned_fraction"),
+           "regret_paper_pruned_plain": a.get("regret_pruned_plain"),
+           "regret_paper_pruned_best": a.get("regret_pruned_best")}
+    out["leave_one_family_out"] = correction.leave_one_family_out(data, epochs=150, seed=7)
+    out["live_search_k8"] = correction.live_search(data, rep["keys"], k=8)
+    out["seconds"] = time.perf_counter() - t0
+    return sur, out
 
 
 def corrected_leg(arch, var, cfg, n_var, n_evals, sur, steps: int) -> dict:

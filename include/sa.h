@@ -359,18 +359,24 @@ sa_status sa_features(const sa_arch *arch, const sa_variants *variants, const sa
 /* Delta for n rows of features (float[n][24]); delta float[n]. */
 sa_status sa_surrogate_fwd(const sa_mlp *mlp, const float *feat, int64_t n, float *delta, void *stream);
 
-/* One training step on a batch of n rows: forward, mean squared error
- * against target float[n], backward (MFMA contractions for dW1 and dW2,
- * per-slab partials summed in a fixed order), and Adam (lr, beta1 0.9,
- * beta2 0.999, eps 1e-8, bias correction for step `step` >= 1) on
- * master / adam_m / adam_v (float[SA_MLP_FLAT] each); the bf16 shadow
- * weights and the biases named by `mlp` are rewritten from the master.
- * grad_out (float[SA_MLP_FLAT], nullable) receives the summed gradients and,
- * at index SA_MLP_PARAMS, the batch loss.  n in [1, 2^20]. */
+/* One training step on a batch of n rows: forward (the same arithmetic as
+ * sa_surrogate_fwd, so Delta equals the served one), mean squared error
+ * against target float[n], backward (dL/dh1 and the weight gradients dW1,
+ * dW2 on the matrix cores, bf16 operands, fp32 sums; each workgroup's sums
+ * added in a fixed order), and Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias correction for step t) on master / adam_m / adam_v
+ * (float[SA_MLP_FLAT] each); the bf16 shadow weights and the biases named by
+ * `mlp` are rewritten from the master.  t is `step` (>= 1) when step_counter
+ * is NULL; otherwise `step` must be 0 and t is read from the device counter
+ * *step_counter (int64, 8-byte aligned, caller-owned) after the step advances
+ * it by one, so that steps replayed from a captured HIP graph each use their
+ * own t.  grad_out (float[SA_MLP_FLAT], nullable) receives the summed
+ * gradients and, at index SA_MLP_PARAMS, the batch loss.  n in [1, 2^20].
+ * Workspace: sa_surrogate_train_workspace_bytes(n) bytes, 256-byte aligned. */
 size_t sa_surrogate_train_workspace_bytes(int64_t n);
 sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step,
-                                  float lr, const float *feat, const float *target, int64_t n, float *grad_out,
-                                  void *workspace, size_t workspace_bytes, void *stream);
+                                  int64_t *step_counter, float lr, const float *feat, const float *target, int64_t n,
+                                  float *grad_out, void *workspace, size_t workspace_bytes, void *stream);
 
 /* The same step with a pairwise ranking loss instead of squared error (the
  * correction's purpose is the order of configurations, Sec. III-C): rows come
@@ -380,12 +386,12 @@ sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_
  * ordered pair (i, j) of a group with log_time[i] < log_time[j] costs
  * softplus(z_i - z_j) = ln(1 + e^(z_i - z_j)); the loss is the mean over each
  * group's pairs, averaged over the groups (a group of equal times adds 0).
- * grad_out's loss entry is that loss. */
+ * grad_out's loss entry is that loss.  step / step_counter as above. */
 #define SA_RANK_GROUP_MAX 1024
 sa_status sa_surrogate_train_step_pairwise(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v,
-                                           int64_t step, float lr, const float *feat, const float *log_time,
-                                           int64_t n, int32_t group, float *grad_out, void *workspace,
-                                           size_t workspace_bytes, void *stream);
+                                           int64_t step, int64_t *step_counter, float lr, const float *feat,
+                                           const float *log_time, int64_t n, int32_t group, float *grad_out,
+                                           void *workspace, size_t workspace_bytes, void *stream);
 
 /* Tile size (evaluations per wave) the next sa_score / sa_occupancy /
  * sa_topk / sa_score_product calls on this thread use; 0 restores the

@@ -151,11 +151,11 @@ def lib():
             L.sa_surrogate_fwd.restype = i32
             L.sa_surrogate_train_workspace_bytes.argtypes = [i64]
             L.sa_surrogate_train_workspace_bytes.restype = sz
-            L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64, vp, vp, sz,
-                                                  vp]
+            L.sa_surrogate_train_step.argtypes = [P(SaMlp), vp, vp, vp, i64, vp, ctypes.c_float, vp, vp, i64, vp, vp,
+                                                  sz, vp]
             L.sa_surrogate_train_step.restype = i32
-            L.sa_surrogate_train_step_pairwise.argtypes = [P(SaMlp), vp, vp, vp, i64, ctypes.c_float, vp, vp, i64,
-                                                           i32, vp, vp, sz, vp]
+            L.sa_surrogate_train_step_pairwise.argtypes = [P(SaMlp), vp, vp, vp, i64, vp, ctypes.c_float, vp, vp,
+                                                           i64, i32, vp, vp, sz, vp]
             L.sa_surrogate_train_step_pairwise.restype = i32
             L.sa_gen_configs.argtypes = [ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp]
             L.sa_gen_configs.restype = i32
@@ -783,6 +783,8 @@ class Surrogate:
         self.mean = torch.as_tensor(np.asarray(mean, np.float32), device=self.device).contiguous()
         self.inv_std = torch.as_tensor(np.asarray(inv_std, np.float32), device=self.device).contiguous()
         self.step_count = 0
+        # device-side step count for steps replayed from a captured graph
+        self.steps_dev = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.W1 = torch.empty((128, 32), dtype=torch.bfloat16, device=self.device)
         self.W2 = torch.empty((128, 128), dtype=torch.bfloat16, device=self.device)
         self.w3 = torch.empty(128, dtype=torch.bfloat16, device=self.device)
@@ -818,22 +820,32 @@ class Surrogate:
                                       _ptr(out, torch.float32, "out"), _stream(stream)))
         return out
 
-    def train_step(self, feat, target, lr: float = 1e-3, stream=None, group: int = 0):
+    def reserve(self, n: int):
+        """Allocate the training workspace for batches of up to n rows now
+        (before a graph capture, which must not allocate it)."""
+        need = int(lib().sa_surrogate_train_workspace_bytes(int(n)))
+        if need and (self._ws is None or self._ws.nbytes < need):
+            self._ws = Workspace(need, self.device)
+
+    def train_step(self, feat, target, lr: float = 1e-3, stream=None, group: int = 0, device_counter: bool = False):
         """One Adam step on the batch; returns the batch loss (0-d device
         tensor).  group = 0: squared error against `target` (the residual);
         group > 0: pairwise ranking loss over groups of `group` consecutive
         rows with `target` the measured log runtime
-        (sa_surrogate_train_step_pairwise)."""
+        (sa_surrogate_train_step_pairwise).  device_counter: Adam's step
+        number comes from (and advances) `steps_dev` on the device, so the
+        call can be captured in a graph and replayed; set steps_dev from
+        step_count before the first such step."""
         torch = _torch()
         n = _feature_rows(feat)
         _numel(target, n, "target")
-        need = int(lib().sa_surrogate_train_workspace_bytes(n))
-        if need and (self._ws is None or self._ws.nbytes < need):
-            self._ws = Workspace(need, self.device)
+        self.reserve(n)
         ws_ptr, ws_bytes = (self._ws.ptr, self._ws.nbytes) if self._ws is not None else (None, 0)
         m = self.struct()
+        step = 0 if device_counter else self.step_count + 1
+        counter = _ptr(self.steps_dev, torch.int64, "steps_dev") if device_counter else None
         common = (ctypes.byref(m), _ptr(self.master, torch.float32), _ptr(self.m, torch.float32),
-                  _ptr(self.v, torch.float32), self.step_count + 1, float(lr), _ptr(feat, torch.float32, "feat"),
+                  _ptr(self.v, torch.float32), step, counter, float(lr), _ptr(feat, torch.float32, "feat"),
                   _ptr(target, torch.float32, "target"), n)
         if group > 0:
             _check(lib().sa_surrogate_train_step_pairwise(*common, int(group), _ptr(self.grad, torch.float32), ws_ptr,
@@ -841,7 +853,10 @@ class Surrogate:
         else:
             _check(lib().sa_surrogate_train_step(*common, _ptr(self.grad, torch.float32), ws_ptr, ws_bytes,
                                                  _stream(stream)))
-        self.step_count += 1
+        if not device_counter:
+            # with the device counter the step happens when the stream (or a
+            # graph replay) runs it: the caller advances step_count then
+            self.step_count += 1
         return self.grad[MLP_PARAMS]
 
     def params(self) -> dict:

@@ -169,12 +169,15 @@ def init_params(seed: int) -> dict:
 
 
 def train(feat, target, mean, inv_std, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
-          device="cuda", log=None, group: int = 0):
+          device="cuda", log=None, group: int = 0, graph: bool = True):
     """Adam over shuffled mini-batches (device tensors feat [n, 24] and
     target [n]); returns the Surrogate and the per-epoch mean loss.
     group = 0: MSE(Delta, r) with rows shuffled; group > 0: the pairwise
     ranking loss with target the log runtime, whole groups of `group`
-    consecutive rows (one instance each) shuffled as units."""
+    consecutive rows (one instance each) shuffled as units.  Each epoch
+    gathers its shuffled rows once into fixed buffers; with `graph` the
+    epoch's steps are captured once in a HIP graph (Adam's step number kept
+    on the device) and replayed every epoch."""
     import torch
 
     sur = api.Surrogate(init_params(seed), mean, inv_std, device)
@@ -184,22 +187,42 @@ def train(feat, target, mean, inv_std, epochs: int = 40, batch: int = 4096, lr: 
     losses = []
     if group > 0:
         batch = max(group, batch // group * group)
+    starts = list(range(0, n - batch + 1 if n >= batch else 1, batch))
+    feat_p, target_p = torch.empty_like(feat), torch.empty_like(target)
+    tot = torch.zeros((), dtype=torch.float32, device=device)
+    sur.reserve(min(batch, n))
+
+    def steps():
+        for b0 in starts:
+            tot.add_(sur.train_step(feat_p[b0:b0 + batch], target_p[b0:b0 + batch], lr=lr, group=group,
+                                    device_counter=graph))
+
+    g = None
     for ep in range(epochs):
         if group > 0:
             g_perm = torch.randperm(n // group, generator=gen, device=device)
             perm = (g_perm[:, None] * group + torch.arange(group, device=device)[None, :]).reshape(-1)
         else:
             perm = torch.randperm(n, generator=gen, device=device)
-        # one gather per epoch; each batch is then a contiguous slice of it
-        feat_p = feat.index_select(0, perm)
-        target_p = target.index_select(0, perm)
-        tot = torch.zeros((), dtype=torch.float32, device=device)
-        nb = 0
-        for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
-            tot += sur.train_step(feat_p[b0:b0 + batch], target_p[b0:b0 + batch], lr=lr, group=group)
-            nb += 1
-        del feat_p, target_p
-        losses.append(float(tot.item()) / max(1, nb))
+        # one gather per epoch into the fixed buffers; each batch is a slice of them
+        torch.index_select(feat, 0, perm, out=feat_p)
+        torch.index_select(target, 0, perm, out=target_p)
+        tot.zero_()
+        if not graph:
+            steps()
+        else:
+            if g is None:
+                sur.steps_dev.fill_(sur.step_count)
+                side = torch.cuda.Stream(device=device)
+                side.wait_stream(torch.cuda.current_stream(device))
+                torch.cuda.synchronize(device)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=side):
+                    steps()
+                torch.cuda.current_stream(device).wait_stream(side)
+            g.replay()
+            sur.step_count += len(starts)
+        losses.append(float(tot.item()) / max(1, len(starts)))
         if log:
             log("epoch %d loss %.5f" % (ep + 1, losses[-1]))
     return sur, losses
@@ -269,7 +292,11 @@ def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, 
 
 
 def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0, device="cuda", log=None,
-        loss: str = "mse"):
+        loss: str = "mse", held_frac: float = 0.1, split=None):
+    """Train on the training instances, evaluate on the held-out ones
+    (`held_frac` of each family, or the explicit (train, held) instance
+    split).  Returns the Surrogate and the report; the report's "keys" entry
+    holds the held-out instances and their plain and corrected keys."""
     import torch
 
     n_inst = int(data["instance"].max()) + 1
@@ -283,7 +310,8 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
         raise ValueError("%d configurations are illegal under the model" % int((~legal).sum()))
     r = residual_targets(np.log(ms), ln_s)
     families = data["family"].reshape(n_inst, N_CFG)[:, 0]
-    tr, held = holdout_split(families, 0.1, seed)
+    tr, held = holdout_split(families, held_frac, seed) if split is None else (np.asarray(split[0]),
+                                                                                 np.asarray(split[1]))
     rows_tr = (tr[:, None] * N_CFG + np.arange(N_CFG)[None, :]).reshape(-1)
     f_np = feat.cpu().numpy()
     mean = f_np[rows_tr].mean(0).astype(np.float32)
@@ -311,10 +339,68 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     j = np.clip(T // ws - 1, 0, 63).astype(np.uint64)
     pruned = ((T % ws == 0) & (((kept >> j) & np.uint64(1)) == 1)).reshape(n_inst, N_CFG)
     rep = evaluate(ms, ln_s, z, held, families, pruned)
+    rep["keys"] = {"held": held, "plain": ln_s[held], "corrected": z[held]}
     rep["train"] = {"loss": loss, "rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
                     "loss_first": losses[0], "loss_last": losses[-1],
                     "target_var": float(np.var(r.reshape(-1)[rows_tr]))}
     return sur, rep
+
+
+def leave_one_family_out(data: dict, **kw) -> dict:
+    """Regret and Spearman on each family when the correction is trained on
+    the other two only (no instance of the family seen in training)."""
+    n_inst = int(data["instance"].max()) + 1
+    families = data["family"].reshape(n_inst, N_CFG)[:, 0]
+    out = {}
+    for f, name in enumerate(FAMILIES):
+        held = np.flatnonzero(families == f)
+        tr = np.flatnonzero(families != f)
+        if held.size == 0 or tr.size == 0:
+            continue
+        _, rep = run(data, split=(tr, held), **kw)
+        a = rep["all"]
+        out[name] = {k: a[k] for k in ("instances", "regret_plain", "regret_corrected", "regret_corrected_ci",
+                                       "spearman_plain", "spearman_corrected")}
+    return out
+
+
+def live_search(data: dict, keys: dict, k: int = 8, device="cuda", seed: int = 0) -> dict:
+    """Model-guided empirical search as the paper intends it (Sec. III-C,
+    Sec. IV-C): for each held-out instance, time the full sweep of its 128
+    configurations, then time only the k configurations each key ranks
+    first, and keep the fastest of those.  Regret is measured against the
+    full sweep's fastest (the survivor's time taken from the same sweep);
+    the time saved is the measured wall clock of the survivors' timing
+    against the sweep's, beside the pruning estimate 1 - k / 128 (t r of
+    Sec. IV-C, every configuration costing the same)."""
+    import torch
+
+    n_inst = int(data["instance"].max()) + 1
+    fam = data["family"].reshape(n_inst, N_CFG)[:, 0]
+    size = data["n"].reshape(n_inst, N_CFG)[:, 0]
+    held = np.asarray(keys["held"])
+    inst = [(FAMILIES[int(fam[i])], int(size[i])) for i in held]
+    timer = runtime_dataset.Timer(inst, torch.cuda.get_device_properties(device).multi_processor_count, device,
+                                  seed=seed)
+    T, U = runtime_dataset.config_grid()
+    wall_full = 0.0
+    wall = {"plain": 0.0, "corrected": 0.0}
+    reg = {"plain": [], "corrected": []}
+    for j, (f, n) in enumerate(inst):
+        ms_full, w_full = timer.time(f, n, T, U)
+        wall_full += w_full
+        for name in ("plain", "corrected"):
+            order = np.argsort(np.asarray(keys[name][j]), kind="stable")[:k]
+            ms_k, w_k = timer.time(f, n, T[order], U[order])
+            wall[name] += w_k
+            best = int(order[int(np.argmin(ms_k))])
+            reg[name].append(float(ms_full[best] / ms_full.min() - 1.0))
+    out = {"instances": len(inst), "k": k, "sweep_seconds": wall_full, "pruned_fraction": 1.0 - k / N_CFG}
+    for name in ("plain", "corrected"):
+        r = np.array(reg[name])
+        out[name] = {"regret": float(r.mean()), "regret_ci": bootstrap_ci(r), "search_seconds": wall[name],
+                     "time_saved": 1.0 - wall[name] / wall_full}
+    return out
 
 
 def time_synthetic(n: int, epochs: int, batch: int, lr: float, seed: int) -> int:
@@ -359,6 +445,7 @@ def main(argv=None):
         return time_synthetic(a.synthetic_rows, a.epochs, a.batch, a.lr, a.seed)
     data = load(a.data) if a.data else runtime_dataset.assemble(a.parts)
     sur, rep = run(data, a.epochs, a.batch, a.lr, a.seed, log=log, loss=a.loss)
+    rep.pop("keys")
     if a.out:
         np.savez(a.out, **{k: np.asarray(v) for k, v in sur.state_dict().items()})
     txt = json.dumps(rep, indent=1)

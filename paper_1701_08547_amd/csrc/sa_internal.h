@@ -131,47 +131,12 @@ struct MlpDev {
   const float *mean, *inv_std;   // [24]
 };
 
-// Flat parameter / gradient layout (fp32 master weights, Adam moments,
-// per-slab gradient partials): W1 | b1 | W2 | b2 | w3 | b3 | loss.
-constexpr int64_t kPartW1 = 0;
-constexpr int64_t kPartB1 = kPartW1 + 128 * 32;
-constexpr int64_t kPartW2 = kPartB1 + 128;
-constexpr int64_t kPartB2 = kPartW2 + 128 * 128;
-constexpr int64_t kPartW3 = kPartB2 + 128;
-constexpr int64_t kPartB3 = kPartW3 + 128;
-constexpr int64_t kPartUsed = kPartB3 + 1;  // parameters
-constexpr int64_t kPartLoss = kPartUsed;    // sum of squared errors
-constexpr int64_t kPartStride = 20992;      // >= kPartLoss + 1, multiple of 256
-
-struct TrainBufs {
-  uint16_t *x;              // [n][32] normalised inputs, bf16
-  float *a1, *a2;           // [n][128] pre-activations
-  uint16_t *h1, *h2;        // [n][128] activations, bf16
-  uint16_t *ga1, *ga2;      // [n][128] dL/da, bf16
-  float *delta, *gdelta, *sq;
-  float *part;              // [slabs][kPartStride]
-};
-
-struct TrainState {
-  float *master, *m, *v;    // [kPartStride]
-};
-
-struct AdamArgs {
-  float lr, beta1, beta2, eps, bc1, bc2;  // bc = 1 - beta^t
-  float inv_n;
-};
-
 hipError_t launch_features(const EvalLaunch &L, float *feat, hipStream_t stream);
 hipError_t launch_suggest(const EvalLaunch &L, uint64_t *kept, hipStream_t stream);
 hipError_t launch_headroom(const EvalLaunch &L, const int32_t *block, const int32_t *regs, int64_t n, int32_t *r_star,
                            int32_t *s_star, hipStream_t stream);
 hipError_t launch_corrected(const EvalLaunch &L, const MlpDev &M, bool has_grid, hipStream_t stream);
 hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *delta, hipStream_t stream);
-int64_t train_slabs(int64_t n);
-// group = 0: squared error against target; group > 0: pairwise ranking loss
-// over groups of `group` consecutive rows with target = log runtime.
-hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,
-                             TrainBufs T, AdamArgs h, float *grad_out, int32_t group, hipStream_t stream);
 
 hipError_t launch_eval(const EvalLaunch &L, Mode mode, bool has_grid, bool topk, hipStream_t stream);
 hipError_t launch_product(const EvalLaunch &L, const KProduct &P, bool has_grid, bool topk, hipStream_t stream);

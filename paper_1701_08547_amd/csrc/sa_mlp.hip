@@ -1,35 +1,28 @@
 // Learned correction of the static model on gfx950: the 24-feature builder,
-// BF16 MFMA forward pass (24 -> 128 -> 128 -> 1, GELU, fp32 accumulation)
-// and the training step (forward, MSE, backward with MFMA weight-gradient
-// contractions, deterministic two-pass reduction, Adam).
+// the BF16 MFMA forward pass for rows of features (24 -> 128 -> 128 -> 1,
+// GELU, fp32 accumulation) and the training step.
 //
-// MFMA tiles use v_mfma_f32_16x16x16_bf16: for a 16x16 output tile D (rows
-// i, columns j) += A (16 x 16, rows i, k) x B (16 x 16, k, columns j), lane l
-// supplies A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16] as
-// four bf16 each, and receives D[4 (l / 16) + 0..3][l % 16].  Operands are
-// kept in LDS row-major with the contraction index contiguous, rows padded
-// so that the sixteen rows a lane group reads fall in different banks.
+// A training step is one fused kernel and one update kernel.  Each workgroup
+// of the fused kernel takes passes of 64 rows, one 16-row tile per wave: the
+// forward pass exactly as inference computes it (same staged weights, GELU
+// pieces and MFMA order, so the training forward's Delta equals the served
+// one bit for bit), the loss gradient, the backward pass in registers (dL/da2,
+// dL/dh1 = W2^T dL/da2 on the matrix cores, dL/da1), and the weight-gradient
+// contractions over the pass's rows from LDS; the workgroup writes its
+// gradient sums once.  The update kernel adds the workgroups' partial sums in
+// a fixed order (deterministic) and applies Adam.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "sa_internal.h"
 #include "sa_mlp_dev.h"
+#include "sa_train.h"
 
 namespace sa {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-constexpr int kH = 128;             // hidden width
-constexpr int kK1 = 32;             // padded input width
-constexpr int kF = 24;              // features
-constexpr int kRows = 64;           // rows per wave block
-constexpr int kLdX = kK1 + 4;       // padded LDS row strides (bf16 elements)
-constexpr int kLdH = kH + 4;
-constexpr int kMlpWaves = 4;        // waves per workgroup
-constexpr int kMlpThreads = 64 * kMlpWaves;
+constexpr int kF = 24;  // features
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -38,126 +31,13 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
-
-// D(16x16) += A[m0.., k0..k0+16) x B, with B given transposed (Bt[n][k]).
-__device__ __forceinline__ v4f mfma_tile(const uint16_t *A, int lda, int m0, const uint16_t *Bt, int ldb, int n0,
-                                         int k0, v4f acc, int lane) {
-  const int r = lane & 15, q = lane >> 4;
-  const v4s a = *(const v4s *)(A + (m0 + r) * lda + k0 + 4 * q);
-  const v4s b = *(const v4s *)(Bt + (n0 + r) * ldb + k0 + 4 * q);
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-}
 
 // Sum over the 16 lanes of a lane group (lanes with equal l / 16).
 __device__ __forceinline__ float sum16(float v) {
 #pragma unroll
   for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
   return v;
-}
-
-struct __align__(16) MlpLds {
-  uint16_t W1[kH * kLdX];  // W1[n][k], k < 32
-  uint16_t W2[kH * kLdH];  // W2[n][k]
-  float w3[kH], b1[kH], b2[kH], b3, mean[kF], inv_std[kF];
-};
-
-struct __align__(16) WaveBufs {
-  uint16_t X[kRows * kLdX];   // normalised inputs, bf16
-  uint16_t H1[kRows * kLdH];  // first hidden layer, bf16
-};
-
-__device__ void load_weights(const MlpDev &M, MlpLds &s, int tid, int nthreads) {
-  for (int i = tid; i < kH * kK1; i += nthreads) s.W1[(i / kK1) * kLdX + (i % kK1)] = M.W1[i];
-  for (int i = tid; i < kH * kH; i += nthreads) s.W2[(i / kH) * kLdH + (i % kH)] = M.W2[i];
-  for (int i = tid; i < kH; i += nthreads) {
-    s.w3[i] = bf2f(M.w3[i]);
-    s.b1[i] = M.b1[i];
-    s.b2[i] = M.b2[i];
-  }
-  for (int i = tid; i < kF; i += nthreads) {
-    s.mean[i] = M.mean[i];
-    s.inv_std[i] = M.inv_std[i];
-  }
-  if (tid == 0) s.b3 = M.b3[0];
-}
-
-// Row `row` of the wave block gets the features f (fp32) normalised and
-// rounded to bf16; the padding inputs are zero.
-__device__ __forceinline__ void put_row(const MlpLds &s, WaveBufs &wb, int row, const float *f) {
-#pragma unroll
-  for (int i = 0; i < kF; ++i) wb.X[row * kLdX + i] = f2bf((f[i] - s.mean[i]) * s.inv_std[i]);
-#pragma unroll
-  for (int i = kF; i < kK1; ++i) wb.X[row * kLdX + i] = 0;
-}
-
-// Optional per-row outputs of the forward pass (training): pre-activations
-// and activations, row-major [row][128].
-struct FwdStash {
-  float *a1, *a2;
-  uint16_t *h1, *h2;
-  int64_t row0;   // global row of the block's first row
-  int64_t n_rows; // rows that exist
-};
-
-// Forward pass of the wave's 64-row block held in wb.X.  Returns Delta of
-// row 4 q + j of M-tile m in d[m][j] on every lane of group q.
-template <bool STASH>
-__device__ void forward_block(const MlpLds &s, WaveBufs &wb, int lane, float (&d)[4][4], const FwdStash &st) {
-  const int r = lane & 15, q = lane >> 4;
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  // layer 1: X (64 x 32) . W1^T -> 128, bias, GELU, bf16
-  for (int nt = 0; nt < kH / 16; ++nt) {
-    v4f acc[4] = {};
-#pragma unroll
-    for (int kk = 0; kk < kK1; kk += 16)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] = mfma_tile(wb.X, kLdX, 16 * m, s.W1, kLdX, 16 * nt, kk, acc[m], lane);
-    const int col = 16 * nt + r;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = 16 * m + 4 * q + j;
-        const float a = acc[m][j] + s.b1[col];
-        const uint16_t h = f2bf(gelu(a));
-        wb.H1[row * kLdH + col] = h;
-        if (STASH && st.row0 + row < st.n_rows) {
-          st.a1[(st.row0 + row) * kH + col] = a;
-          st.h1[(st.row0 + row) * kH + col] = h;
-        }
-      }
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  // layer 2 with layer 3 folded into its epilogue
-  float part[4][4] = {};
-  for (int nt = 0; nt < kH / 16; ++nt) {
-    v4f acc[4] = {};
-    for (int kk = 0; kk < kH; kk += 16)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] = mfma_tile(wb.H1, kLdH, 16 * m, s.W2, kLdH, 16 * nt, kk, acc[m], lane);
-    const int col = 16 * nt + r;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = 16 * m + 4 * q + j;
-        const float a = acc[m][j] + s.b2[col];
-        const uint16_t h = f2bf(gelu(a));
-        part[m][j] += bf2f(h) * s.w3[col];
-        if (STASH && st.row0 + row < st.n_rows) {
-          st.a2[(st.row0 + row) * kH + col] = a;
-          st.h2[(st.row0 + row) * kH + col] = h;
-        }
-      }
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) d[m][j] = sum16(part[m][j]) + s.b3;
 }
 
 // ---------------------------------------------------------------- features
@@ -284,48 +164,250 @@ __global__ __launch_bounds__(64 * kFwdWaves) void sa_mlp_fwd_kernel(MlpDev M, co
 
 // ---------------------------------------------------------------- training
 
-// Forward over the batch with every activation stashed, the loss terms and
-// dL/dDelta = 2 (Delta - r) / n.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void sa_train_fwd_kernel(MlpDev M, const float *feat, const float *target,
-                                                                  int64_t n, TrainBufs T) {
-  __shared__ MlpLds s;
-  __shared__ WaveBufs wbuf[WAVES];
+constexpr int kTrainWaves = 4;                // one 16-row tile per wave
+constexpr int kTrainRows = 16 * kTrainWaves;  // rows per pass of a workgroup
+constexpr int kTrainThreads = 64 * kTrainWaves;
+constexpr int kMaxPartials = 256;             // workgroups (gradient partials) of one step
+constexpr int kLdR = kTrainRows + 8;          // row stride of the per-pass blocks (bf16), padded
+
+struct __align__(16) TrainLds {
+  MlpLdsT f;                        // forward: the inference staging (x64 weights, GELU pieces)
+  uint16_t W2b[kMH * kLdW2];        // backward: W2b[k][p] = W2[w2_column(p)][k]
+  float w3[kMH];                    // w3 as the forward uses it (its bf16 value)
+  uint16_t gA2t[kMH * kLdR];        // dL/da2 [hidden][row of the pass], bf16
+  uint16_t gA1t[kMH * kLdR];        // dL/da1
+  uint16_t H1t[kMH * kLdR];         // h1
+  uint16_t Xt[kMK * kLdR];          // normalised inputs, columns 24..31 zero
+  float sums[kTrainWaves][3][kMH];  // per-wave column sums: b1, b2, w3 gradients
+  float tail[kTrainWaves][2];       // per-wave b3 gradient and loss
+};
+
+// a of a scaled pre-activation t = 64 a + 512.
+__device__ __forceinline__ float unscale(float t) { return (t - kTOrigin) * (1.0f / kTScale); }
+
+// LOSS 0: squared error against target (dL/dDelta = 2 (Delta - r) / n).
+// LOSS 1: dL/dDelta and the loss terms given per row (pairwise ranking loss,
+// computed beforehand from this step's Delta).
+template <int LOSS>
+__global__ __launch_bounds__(kTrainThreads) void sa_train_kernel(MlpDev M, const float *feat, const float *target,
+                                                                 int64_t n, TrainBufs T, int64_t *step_counter) {
+  __shared__ TrainLds s;
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-  load_weights(M, s, tid, 64 * WAVES);
-  __syncthreads();
-  WaveBufs &wb = wbuf[w];
-  const int64_t n_blocks = (n + kRows - 1) / kRows;
-  for (int64_t blk = (int64_t)blockIdx.x * WAVES + w; blk < n_blocks; blk += (int64_t)gridDim.x * WAVES) {
-    const int64_t row = blk * kRows + lane;
-    float f[kF];
-#pragma unroll
-    for (int i = 0; i < kF; ++i) f[i] = row < n ? feat[row * kF + i] : 0.0f;
-    put_row(s, wb, lane, f);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    if (row < n)
-      for (int i = 0; i < kK1; ++i) T.x[row * kK1 + i] = wb.X[lane * kLdX + i];
-    float d[4][4];
-    forward_block<true>(s, wb, lane, d, FwdStash{T.a1, T.a2, T.h1, T.h2, blk * kRows, n});
-    const int r = lane & 15, q = lane >> 4;
-    if (r == 0) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int64_t rr = blk * kRows + 16 * m + 4 * q + j;
-          if (rr < n) {
-            const float e = d[m][j] - target[rr];
-            T.delta[rr] = d[m][j];
-            T.gdelta[rr] = 2.0f * e / (float)n;
-            T.sq[rr] = e * e;
-          }
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  const int r = lane & 15, q = lane >> 4;
+  load_weights_t(M, s.f, tid, kTrainThreads);
+  for (int i = tid; i < kMH * kMH; i += kTrainThreads) {
+    const int k = i / kMH, p = i % kMH;
+    s.W2b[k * kLdW2 + p] = M.W2[w2_column(p) * kMH + k];
   }
+  for (int i = tid; i < kMH; i += kTrainThreads) s.w3[i] = bf2f(M.w3[i]);
+  if (step_counter && blockIdx.x == 0 && tid == 0) *step_counter += 1;  // read by the update kernel
+  __syncthreads();
+  const float inv_n2 = 2.0f / (float)n;
+  // per-lane running sums over this workgroup's rows (reduced at the end)
+  float g_b1[8][4], g_b2[8][4], g_w3[8][4];
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g_b1[t][j] = g_b2[t][j] = g_w3[t][j] = 0.0f;
+  float g_b3 = 0.0f, loss = 0.0f;
+  f32x4_t accW2[16], accW1[4];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) accW2[i] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) accW1[i] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  const int col = 16 * w + r;  // this lane's row within the pass
+
+  for (int64_t base = (int64_t)blockIdx.x * kTrainRows; base < n; base += (int64_t)gridDim.x * kTrainRows) {
+    const int64_t row = base + col;
+    const bool in = row < n;
+    // inputs: slice q (features 8 q .. 8 q + 7) of this lane's row, as inference packs them
+    u32x4_t xb = {0u, 0u, 0u, 0u};
+    if (q < 3 && in) {
+      const float *fr = feat + row * kF + 8 * q;
+      const float *mu = s.f.mean + 8 * q, *is = s.f.inv_std + 8 * q;
+      uint32_t p[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        p[i] = pack_bf16((fr[2 * i] - mu[2 * i]) * is[2 * i], (fr[2 * i + 1] - mu[2 * i + 1]) * is[2 * i + 1]);
+      xb = u32x4_t{p[0], p[1], p[2], p[3]};
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s.Xt[(8 * q + 2 * i) * kLdR + col] = (uint16_t)(xb[i] & 0xFFFFu);
+      s.Xt[(8 * q + 2 * i + 1) * kLdR + col] = (uint16_t)(xb[i] >> 16);
+    }
+    // layer 1 (scaled pre-activations kept for the backward pass)
+    f32x4_t t1[8];
+    uint32_t h1[8][2];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const u32x4_t a = *(const u32x4_t *)(s.f.W1 + (16 * t + r) * kLdW1 + 8 * q);
+      const f32x4_t bias = *(const f32x4_t *)(s.f.b1 + 16 * t + 4 * q);
+      t1[t] = mfma32(a, xb, bias);
+      float v[4] = {t1[t][0], t1[t][1], t1[t][2], t1[t][3]};
+      gelu_t_n<4>(v, s.f.gelu);
+      h1[t][0] = pack_bf16(v[0], v[1]);
+      h1[t][1] = pack_bf16(v[2], v[3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        s.H1t[(16 * t + 4 * q + j) * kLdR + col] = (uint16_t)(h1[t][j >> 1] >> (16 * (j & 1)));
+    }
+    // layer 2
+    f32x4_t t2[8];
+    uint32_t h2[8][2];
+#pragma unroll
+    for (int ot = 0; ot < 8; ++ot) {
+      f32x4_t acc = *(const f32x4_t *)(s.f.b2 + 16 * ot + 4 * q);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const u32x4_t a = *(const u32x4_t *)(s.f.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
+        acc = mfma32(a, u32x4_t{h1[2 * c][0], h1[2 * c][1], h1[2 * c + 1][0], h1[2 * c + 1][1]}, acc);
+      }
+      t2[ot] = acc;
+      float v[4] = {acc[0], acc[1], acc[2], acc[3]};
+      gelu_t_n<4>(v, s.f.gelu);
+      h2[ot][0] = pack_bf16(v[0], v[1]);
+      h2[ot][1] = pack_bf16(v[2], v[3]);
+    }
+    // layer 3: every A row is w3, so each lane of column r receives Delta of row r
+    f32x4_t acc3 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c3 = 0; c3 < 4; ++c3) {
+      const u32x4_t a3 = *(const u32x4_t *)(s.f.w3p + 32 * c3 + 8 * q);
+      acc3 = mfma32(a3, u32x4_t{h2[2 * c3][0], h2[2 * c3][1], h2[2 * c3 + 1][0], h2[2 * c3 + 1][1]}, acc3);
+    }
+    const float delta = acc3[0] + s.f.b3;
+    // the loss gradient of this lane's row
+    float gd = 0.0f;
+    if (in) {
+      if constexpr (LOSS == 0) {
+        const float e = delta - target[row];
+        gd = inv_n2 * e;
+        if (q == 0) loss += e * e;
+      } else {
+        gd = T.gdelta[row];
+        if (q == 0) loss += T.loss[row];
+      }
+    }
+    if (q == 0) g_b3 += gd;
+    // dL/da2 = dL/dDelta w3 GELU'(a2), packed as the next contraction's B operand
+    uint32_t g2[8][2];
+#pragma unroll
+    for (int ot = 0; ot < 8; ++ot) {
+      float g[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int hid = 16 * ot + 4 * q + j;
+        const float hv = bf2f((uint16_t)(h2[ot][j >> 1] >> (16 * (j & 1))));
+        g[j] = gd * s.w3[hid] * gelu_grad(unscale(t2[ot][j]));
+        g_b2[ot][j] += g[j];
+        g_w3[ot][j] += gd * hv;
+      }
+      g2[ot][0] = pack_bf16(g[0], g[1]);
+      g2[ot][1] = pack_bf16(g[2], g[3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        s.gA2t[(16 * ot + 4 * q + j) * kLdR + col] = (uint16_t)(g2[ot][j >> 1] >> (16 * (j & 1)));
+    }
+    // dL/dh1 = W2^T dL/da2 (matrix cores), then dL/da1 = dL/dh1 GELU'(a1)
+#pragma unroll
+    for (int kt = 0; kt < 8; ++kt) {
+      f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const u32x4_t a = *(const u32x4_t *)(s.W2b + (16 * kt + r) * kLdW2 + 32 * c + 8 * q);
+        acc = mfma32(a, u32x4_t{g2[2 * c][0], g2[2 * c][1], g2[2 * c + 1][0], g2[2 * c + 1][1]}, acc);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float g = acc[j] * gelu_grad(unscale(t1[kt][j]));
+        g_b1[kt][j] += g;
+        s.gA1t[(16 * kt + 4 * q + j) * kLdR + col] = f2bf(g);
+      }
+    }
+    __syncthreads();
+    // weight gradients over the pass's 64 rows: dW2 = dA2^T H1 (64 tiles, 16 per
+    // wave), dW1 = dA1^T X (16 tiles, 4 per wave)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int tile = 16 * w + i, mt = tile >> 3, nt = tile & 7;
+#pragma unroll
+      for (int kk = 0; kk < kTrainRows; kk += 32) {
+        const u32x4_t a = *(const u32x4_t *)(s.gA2t + (16 * mt + r) * kLdR + kk + 8 * q);
+        const u32x4_t b = *(const u32x4_t *)(s.H1t + (16 * nt + r) * kLdR + kk + 8 * q);
+        accW2[i] = mfma32(a, b, accW2[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int tile = 4 * w + i, mt = tile >> 1, nt = tile & 1;
+#pragma unroll
+      for (int kk = 0; kk < kTrainRows; kk += 32) {
+        const u32x4_t a = *(const u32x4_t *)(s.gA1t + (16 * mt + r) * kLdR + kk + 8 * q);
+        const u32x4_t b = *(const u32x4_t *)(s.Xt + (16 * nt + r) * kLdR + kk + 8 * q);
+        accW1[i] = mfma32(a, b, accW1[i]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // this workgroup's sums: the weight tiles as they stand, the column sums
+  // reduced over each wave's 16 rows and then over the waves
+  float *part = T.part + (int64_t)blockIdx.x * kPartStride;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int tile = 16 * w + i, mt = tile >> 3, nt = tile & 7;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[kPartW2 + (16 * mt + 4 * q + j) * kMH + 16 * nt + r] = accW2[i][j];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int tile = 4 * w + i, mt = tile >> 1, nt = tile & 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[kPartW1 + (16 * mt + 4 * q + j) * kMK + 16 * nt + r] = accW1[i][j];
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float b1 = sum16(g_b1[t][j]), b2 = sum16(g_b2[t][j]), w3 = sum16(g_w3[t][j]);
+      if (r == 0) {
+        const int hid = 16 * t + 4 * q + j;
+        s.sums[w][0][hid] = b1;
+        s.sums[w][1][hid] = b2;
+        s.sums[w][2][hid] = w3;
+      }
+    }
+  // q == 0 lanes hold one row each: sum over the wave's 16 rows
+  const float b3w = sum16(g_b3), lw = sum16(loss);
+  if (lane == 0) {
+    s.tail[w][0] = b3w;
+    s.tail[w][1] = lw;
+  }
+  __syncthreads();
+  for (int i = tid; i < kMH; i += kTrainThreads) {
+    float b1 = 0.0f, b2 = 0.0f, w3 = 0.0f;
+#pragma unroll
+    for (int v = 0; v < kTrainWaves; ++v) {
+      b1 += s.sums[v][0][i];
+      b2 += s.sums[v][1][i];
+      w3 += s.sums[v][2][i];
+    }
+    part[kPartB1 + i] = b1;
+    part[kPartB2 + i] = b2;
+    part[kPartW3 + i] = w3;
+  }
+  if (tid == 0) {
+    float b3 = 0.0f, l = 0.0f;
+#pragma unroll
+    for (int v = 0; v < kTrainWaves; ++v) {
+      b3 += s.tail[v][0];
+      l += s.tail[v][1];
+    }
+    part[kPartB3] = b3;
+    part[kPartLoss] = l;
+  }
+  for (int64_t i = kPartLoss + 1 + tid; i < kPartStride; i += kTrainThreads) part[i] = 0.0f;
 }
 
 // Pairwise ranking loss, one workgroup per group of `group` consecutive rows
@@ -335,7 +417,6 @@ __global__ __launch_bounds__(64 * WAVES) void sa_train_fwd_kernel(MlpDev M, cons
 // over pairs within each group, averaged over the groups.  dL/dz_i =
 // (sum over j after i of sigma(z_i - z_j) - sum over j before i of
 // sigma(z_j - z_i)) / (groups x pairs of the group); dL/dDelta = dL/dz.
-// Overwrites the squared-error terms the forward kernel left.
 __global__ __launch_bounds__(256) void sa_train_rank_kernel(const float *feat, const float *target, int32_t group,
                                                             float inv_groups, TrainBufs T) {
   extern __shared__ float zy[];  // z[group], y[group]
@@ -367,171 +448,48 @@ __global__ __launch_bounds__(256) void sa_train_rank_kernel(const float *feat, c
       }
     }
     T.gdelta[g0 + i] = g * w;
-    T.sq[g0 + i] = l * w;
+    T.loss[g0 + i] = l * w;
   }
 }
 
-// Per row: dA2 = (dDelta w3) * GELU'(a2), dH1 = dA2 W2 (MFMA), dA1 = dH1 *
-// GELU'(a1); dA2, dA1 stored bf16 for the weight-gradient contractions.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void sa_train_bwd_rows_kernel(MlpDev M, int64_t n, TrainBufs T) {
-  __shared__ uint16_t W2t[kH * kLdH];  // W2 transposed: W2t[k][n] = W2[n][k]
-  __shared__ float w3[kH];
-  __shared__ uint16_t G2[WAVES][kRows * kLdH];
-  const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-  for (int i = tid; i < kH * kH; i += 64 * WAVES) {
-    const int nn = i / kH, kk = i % kH;
-    W2t[kk * kLdH + nn] = M.W2[i];
-  }
-  for (int i = tid; i < kH; i += 64 * WAVES) w3[i] = bf2f(M.w3[i]);
-  __syncthreads();
-  uint16_t *g2 = G2[w];
-  const int r = lane & 15, q = lane >> 4;
-  const int64_t n_blocks = (n + kRows - 1) / kRows;
-  for (int64_t blk = (int64_t)blockIdx.x * WAVES + w; blk < n_blocks; blk += (int64_t)gridDim.x * WAVES) {
-    const int64_t row = blk * kRows + lane;
-    const float gd = row < n ? T.gdelta[row] : 0.0f;
-    for (int c = 0; c < kH; ++c) {
-      const float a2 = row < n ? T.a2[row * kH + c] : 0.0f;
-      const uint16_t g = f2bf(gd * w3[c] * gelu_grad(a2));
-      g2[lane * kLdH + c] = g;
-      if (row < n) T.ga2[row * kH + c] = g;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (int nt = 0; nt < kH / 16; ++nt) {
-      v4f acc[4] = {};
-      for (int kk = 0; kk < kH; kk += 16)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m] = mfma_tile(g2, kLdH, 16 * m, W2t, kLdH, 16 * nt, kk, acc[m], lane);
-      const int col = 16 * nt + r;
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int64_t rr = blk * kRows + 16 * m + 4 * q + j;
-          if (rr < n) T.ga1[rr * kH + col] = f2bf(acc[m][j] * gelu_grad(T.a1[rr * kH + col]));
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  }
-}
-
-// Weight gradients, one workgroup per slab of kSlab rows: the slab's
-// contributions to dW2 = dA2^T H1, dW1 = dA1^T X (MFMA over the rows) and to
-// the bias / output-layer sums, written as fp32 partials part[slab][...].
-constexpr int kSlab = 64;  // one 64-row chunk per workgroup: a 4,096-row step spreads over 64 workgroups
-constexpr int kLdT = 64 + 4;  // transposed 64-row chunk, padded
-
-__global__ __launch_bounds__(kMlpThreads) void sa_train_wgrad_kernel(int64_t n, TrainBufs T) {
-  __shared__ uint16_t gA2t[kH * kLdT];  // [n][rows of chunk]
-  __shared__ uint16_t gA1t[kH * kLdT];
-  __shared__ uint16_t H1t[kH * kLdT];   // [k][rows]
-  __shared__ uint16_t Xt[kK1 * kLdT];
-  const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-  const int64_t slab = blockIdx.x;
-  const int64_t r0 = slab * kSlab;
-  float *part = T.part + slab * kPartStride;
-  // each wave owns output tiles: dW2 has 64 tiles (8 x 8), dW1 16 (8 x 2)
-  v4f accW2[16] = {};
-  v4f accW1[4] = {};
-  float sums_b1 = 0.f, sums_b2 = 0.f, sums_w3 = 0.f, sum_b3 = 0.f, sum_sq = 0.f;  // thread tid < 128 owns column tid
-  for (int64_t c0 = r0; c0 < r0 + kSlab; c0 += 64) {
-    __syncthreads();
-    for (int i = tid; i < 64 * kH; i += kMlpThreads) {
-      const int rr = i / kH, cc = i % kH;
-      const int64_t row = c0 + rr;
-      const bool in = row < n;
-      gA2t[cc * kLdT + rr] = in ? T.ga2[row * kH + cc] : 0;
-      gA1t[cc * kLdT + rr] = in ? T.ga1[row * kH + cc] : 0;
-      H1t[cc * kLdT + rr] = in ? T.h1[row * kH + cc] : 0;
-    }
-    for (int i = tid; i < 64 * kK1; i += kMlpThreads) {
-      const int rr = i / kK1, cc = i % kK1;
-      const int64_t row = c0 + rr;
-      Xt[cc * kLdT + rr] = row < n ? T.x[row * kK1 + cc] : 0;
-    }
-    __syncthreads();
-    // dW2[nn][kk] += sum_rows gA2[row][nn] H1[row][kk]: A = gA2t ([nn][rows]), Bt = H1t ([kk][rows])
-    for (int t = 0; t < 16; ++t) {
-      const int tile = w * 16 + t, mt = tile / 8, nt = tile % 8;
-#pragma unroll
-      for (int kk = 0; kk < 64; kk += 16) accW2[t] = mfma_tile(gA2t, kLdT, 16 * mt, H1t, kLdT, 16 * nt, kk, accW2[t], lane);
-    }
-    for (int t = 0; t < 4; ++t) {
-      const int tile = w * 4 + t, mt = tile / 2, nt = tile % 2;
-#pragma unroll
-      for (int kk = 0; kk < 64; kk += 16) accW1[t] = mfma_tile(gA1t, kLdT, 16 * mt, Xt, kLdT, 16 * nt, kk, accW1[t], lane);
-    }
-    if (tid < kH) {
-      for (int rr = 0; rr < 64; ++rr) {
-        const int64_t row = c0 + rr;
-        if (row >= n) break;
-        sums_b1 += bf2f(gA1t[tid * kLdT + rr]);
-        sums_b2 += bf2f(gA2t[tid * kLdT + rr]);
-        sums_w3 += bf2f(T.h2[row * kH + tid]) * T.gdelta[row];
-        if (tid == 0) {
-          sum_b3 += T.gdelta[row];
-          sum_sq += T.sq[row];
-        }
-      }
-    }
-  }
-  const int r = lane & 15, q = lane >> 4;
-  for (int t = 0; t < 16; ++t) {
-    const int tile = w * 16 + t, mt = tile / 8, nt = tile % 8;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) part[kPartW2 + (16 * mt + 4 * q + j) * kH + 16 * nt + r] = accW2[t][j];
-  }
-  for (int t = 0; t < 4; ++t) {
-    const int tile = w * 4 + t, mt = tile / 2, nt = tile % 2;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) part[kPartW1 + (16 * mt + 4 * q + j) * kK1 + 16 * nt + r] = accW1[t][j];
-  }
-  if (tid < kH) {
-    part[kPartB1 + tid] = sums_b1;
-    part[kPartB2 + tid] = sums_b2;
-    part[kPartW3 + tid] = sums_w3;
-  }
-  if (tid == 0) {
-    part[kPartB3] = sum_b3;
-    part[kPartLoss] = sum_sq;
-  }
-  // untouched tail of the partial row
-  for (int64_t i = kPartLoss + 1 + tid; i < kPartStride; i += kMlpThreads) part[i] = 0.0f;
-}
-
-// Sum the slabs' partials (fixed order: deterministic), then Adam on the fp32
-// master weights and the bf16 shadow.  One thread per parameter.
-__global__ void sa_train_adam_kernel(TrainState S, MlpDev Mw, const float *part, int64_t n_slabs, AdamArgs h,
+// Sum the workgroups' partials (fixed order: deterministic), then Adam on the
+// fp32 master weights and the bf16 shadow.  One thread per parameter.  With
+// a step counter, the bias corrections follow the count the training kernel
+// has just advanced.
+__global__ void sa_train_adam_kernel(TrainState S, MlpDev Mw, const float *part, int64_t n_parts, AdamArgs h,
                                      float *grad_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kPartStride) return;
   float g = 0.0f;
-  for (int64_t s = 0; s < n_slabs; ++s) g += part[s * kPartStride + i];
+  for (int64_t p = 0; p < n_parts; ++p) g += part[p * kPartStride + i];
   if (grad_out) grad_out[i] = i == kPartLoss ? g * h.inv_n : g;
   if (i >= kPartUsed) return;
+  float bc1 = h.bc1, bc2 = h.bc2;
+  if (h.step_counter) {
+    const double t = (double)*h.step_counter;
+    bc1 = (float)(1.0 - pow((double)h.beta1, t));
+    bc2 = (float)(1.0 - pow((double)h.beta2, t));
+  }
   const float m = h.beta1 * S.m[i] + (1.0f - h.beta1) * g;
   const float v = h.beta2 * S.v[i] + (1.0f - h.beta2) * g * g;
   S.m[i] = m;
   S.v[i] = v;
-  const float mh = m / h.bc1, vh = v / h.bc2;
+  const float mh = m / bc1, vh = v / bc2;
   const float p = S.master[i] - h.lr * mh / (sqrtf(vh) + h.eps);
   S.master[i] = p;
   uint16_t *W1 = (uint16_t *)Mw.W1, *W2 = (uint16_t *)Mw.W2, *w3 = (uint16_t *)Mw.w3;
   float *b1 = (float *)Mw.b1, *b2 = (float *)Mw.b2, *b3 = (float *)Mw.b3;
-  if (i < kPartW1 + kH * kK1 && i >= kPartW1) {
+  if (i < kPartW1 + kMH * kMK && i >= kPartW1) {
     const int64_t j = i - kPartW1;
-    W1[j] = (j % kK1) < kF ? f2bf(p) : 0;  // padding inputs stay zero
-    if ((j % kK1) >= kF) S.master[i] = 0.0f;
-  } else if (i >= kPartW2 && i < kPartW2 + kH * kH) {
+    W1[j] = (j % kMK) < kF ? f2bf(p) : 0;  // padding inputs stay zero
+    if ((j % kMK) >= kF) S.master[i] = 0.0f;
+  } else if (i >= kPartW2 && i < kPartW2 + kMH * kMH) {
     W2[i - kPartW2] = f2bf(p);
-  } else if (i >= kPartW3 && i < kPartW3 + kH) {
+  } else if (i >= kPartW3 && i < kPartW3 + kMH) {
     w3[i - kPartW3] = f2bf(p);
-  } else if (i >= kPartB1 && i < kPartB1 + kH) {
+  } else if (i >= kPartB1 && i < kPartB1 + kMH) {
     b1[i - kPartB1] = p;
-  } else if (i >= kPartB2 && i < kPartB2 + kH) {
+  } else if (i >= kPartB2 && i < kPartB2 + kMH) {
     b2[i - kPartB2] = p;
   } else if (i == kPartB3) {
     b3[0] = p;
@@ -557,42 +515,33 @@ hipError_t launch_mlp_fwd(const MlpDev &M, const float *feat, int64_t n, float *
   return hipGetLastError();
 }
 
-int64_t train_slabs(int64_t n) { return (n + kSlab - 1) / kSlab; }
+int64_t train_partials(int64_t n) {
+  const int64_t passes = (n + kTrainRows - 1) / kTrainRows;
+  return passes < kMaxPartials ? passes : kMaxPartials;
+}
 
 hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, const float *target, int64_t n,
                              TrainBufs T, AdamArgs h, float *grad_out, int32_t group, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  // Batches of up to 1,024 row blocks run one wave per workgroup, so that
-  // their few row blocks spread over as many compute units; larger ones
-  // share each workgroup's staged weights among four waves.
-  const int64_t n_blocks = (n + kRows - 1) / kRows;
-  const bool narrow = n_blocks <= 1024;
-  int64_t grid = narrow ? n_blocks : (n_blocks + kMlpWaves - 1) / kMlpWaves;
-  if (grid > 4096) grid = 4096;
-  if (narrow)
-    hipLaunchKernelGGL(sa_train_fwd_kernel<1>, dim3((uint32_t)grid), dim3(64), 0, stream, M, feat, target, n, T);
-  else
-    hipLaunchKernelGGL(sa_train_fwd_kernel<kMlpWaves>, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, feat,
-                       target, n, T);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const int64_t parts = train_partials(n);
+  hipError_t e;
   if (group > 0) {
+    // this step's Delta (the same values the fused kernel recomputes), then the
+    // ranking loss's per-row gradients
+    if ((e = launch_mlp_fwd(M, feat, n, T.delta, stream)) != hipSuccess) return e;
     const int64_t groups = n / group;
     hipLaunchKernelGGL(sa_train_rank_kernel, dim3((uint32_t)groups), dim3(256), (size_t)(2 * group) * sizeof(float),
                        stream, feat, target, group, 1.0f / (float)groups, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(sa_train_kernel<1>, dim3((uint32_t)parts), dim3(kTrainThreads), 0, stream, M, feat, target, n, T,
+                       h.step_counter);
+  } else {
+    hipLaunchKernelGGL(sa_train_kernel<0>, dim3((uint32_t)parts), dim3(kTrainThreads), 0, stream, M, feat, target, n, T,
+                       h.step_counter);
   }
-  if (narrow)
-    hipLaunchKernelGGL(sa_train_bwd_rows_kernel<1>, dim3((uint32_t)grid), dim3(64), 0, stream, M, n, T);
-  else
-    hipLaunchKernelGGL(sa_train_bwd_rows_kernel<kMlpWaves>, dim3((uint32_t)grid), dim3(kMlpThreads), 0, stream, M, n,
-                       T);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t slabs = train_slabs(n);
-  hipLaunchKernelGGL(sa_train_wgrad_kernel, dim3((uint32_t)slabs), dim3(kMlpThreads), 0, stream, n, T);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(sa_train_adam_kernel, dim3((uint32_t)((kPartStride + 255) / 256)), dim3(256), 0, stream, S, M,
-                     T.part, slabs, h, grad_out);
+                     T.part, parts, h, grad_out);
   return hipGetLastError();
 }
 

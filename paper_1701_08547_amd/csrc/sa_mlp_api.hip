@@ -6,6 +6,7 @@
 
 #include "sa.h"
 #include "sa_internal.h"
+#include "sa_train.h"
 
 namespace sa_detail {
 sa_status fail(sa_status st, const char *fmt, ...);
@@ -42,20 +43,20 @@ static_assert(sa::kPartStride == SA_MLP_FLAT, "flat layout");
 
 namespace {
 
-// Workspace carve-up of one training step of n rows.
+// Workspace carve-up of one training step of n rows: Delta, dL/dDelta and
+// the per-row loss terms (pairwise loss), then the workgroups' gradient
+// partials.
 struct TrainLayout {
-  size_t off[12];
+  size_t off[4];
   size_t total;
 };
 
 TrainLayout train_layout(int64_t n) {
-  const size_t sizes[11] = {(size_t)n * 32 * 2, (size_t)n * 128 * 4, (size_t)n * 128 * 4, (size_t)n * 128 * 2,
-                            (size_t)n * 128 * 2, (size_t)n * 128 * 2, (size_t)n * 128 * 2, (size_t)n * 4,
-                            (size_t)n * 4, (size_t)n * 4,
-                            (size_t)sa::train_slabs(n) * (size_t)sa::kPartStride * 4};
+  const size_t sizes[4] = {(size_t)n * 4, (size_t)n * 4, (size_t)n * 4,
+                           (size_t)sa::train_partials(n) * (size_t)sa::kPartStride * 4};
   TrainLayout L{};
   size_t o = 0;
-  for (int i = 0; i < 11; ++i) {
+  for (int i = 0; i < 4; ++i) {
     L.off[i] = o;
     o += (sizes[i] + 255) / 256 * 256;
   }
@@ -111,14 +112,19 @@ size_t sa_surrogate_train_workspace_bytes(int64_t n) {
 
 namespace {
 
-sa_status train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step, float lr,
-                     const float *feat, const float *target, int64_t n, float *grad_out, int32_t group,
-                     void *workspace, size_t workspace_bytes, void *stream) {
+sa_status train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step,
+                     int64_t *step_counter, float lr, const float *feat, const float *target, int64_t n,
+                     float *grad_out, int32_t group, void *workspace, size_t workspace_bytes, void *stream) {
   sa_status st;
   if ((st = check_mlp(mlp)) != SA_OK) return st;
   if (!master || !adam_m || !adam_v || !feat || !target) return fail(SA_ERR_ARG, "NULL argument");
   if (n < 1 || n > (1 << 20)) return fail(SA_ERR_ARG, "n = %lld outside [1, 2^20]", (long long)n);
-  if (step < 1) return fail(SA_ERR_ARG, "step must be >= 1");
+  if (step_counter) {
+    if (step != 0) return fail(SA_ERR_ARG, "step must be 0 when a step counter is given");
+    if ((uintptr_t)step_counter % 8) return fail(SA_ERR_ALIGN, "step_counter not 8-byte aligned");
+  } else if (step < 1) {
+    return fail(SA_ERR_ARG, "step must be >= 1");
+  }
   if (!(lr > 0.0f) || !isfinite(lr)) return fail(SA_ERR_ARG, "lr must be finite and > 0");
   const TrainLayout TL = train_layout(n);
   if (!workspace) return fail(SA_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", TL.total);
@@ -126,24 +132,18 @@ sa_status train_step(const sa_mlp *mlp, float *master, float *adam_m, float *ada
   if (workspace_bytes < TL.total) return fail(SA_ERR_WORKSPACE, "workspace %zu < %zu bytes", workspace_bytes, TL.total);
   char *w = (char *)workspace;
   sa::TrainBufs T;
-  T.x = (uint16_t *)(w + TL.off[0]);
-  T.a1 = (float *)(w + TL.off[1]);
-  T.a2 = (float *)(w + TL.off[2]);
-  T.h1 = (uint16_t *)(w + TL.off[3]);
-  T.h2 = (uint16_t *)(w + TL.off[4]);
-  T.ga1 = (uint16_t *)(w + TL.off[5]);
-  T.ga2 = (uint16_t *)(w + TL.off[6]);
-  T.delta = (float *)(w + TL.off[7]);
-  T.gdelta = (float *)(w + TL.off[8]);
-  T.sq = (float *)(w + TL.off[9]);
-  T.part = (float *)(w + TL.off[10]);
+  T.delta = (float *)(w + TL.off[0]);
+  T.gdelta = (float *)(w + TL.off[1]);
+  T.loss = (float *)(w + TL.off[2]);
+  T.part = (float *)(w + TL.off[3]);
   sa::AdamArgs h;
   h.lr = lr;
   h.beta1 = 0.9f;
   h.beta2 = 0.999f;
   h.eps = 1e-8f;
-  h.bc1 = (float)(1.0 - pow(0.9, (double)step));
-  h.bc2 = (float)(1.0 - pow(0.999, (double)step));
+  h.bc1 = step > 0 ? (float)(1.0 - pow(0.9, (double)step)) : 1.0f;
+  h.bc2 = step > 0 ? (float)(1.0 - pow(0.999, (double)step)) : 1.0f;
+  h.step_counter = step_counter;
   // the ranking loss's per-row terms already carry its normalisation
   h.inv_n = group > 0 ? 1.0f : 1.0f / (float)n;
   hipError_t e = sa::launch_train_step(mlp_dev(mlp), sa::TrainState{master, adam_m, adam_v}, feat, target, n, T, h,
@@ -156,20 +156,20 @@ sa_status train_step(const sa_mlp *mlp, float *master, float *adam_m, float *ada
 extern "C" {
 
 sa_status sa_surrogate_train_step(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v, int64_t step,
-                                  float lr, const float *feat, const float *target, int64_t n, float *grad_out,
-                                  void *workspace, size_t workspace_bytes, void *stream) {
-  return train_step(mlp, master, adam_m, adam_v, step, lr, feat, target, n, grad_out, 0, workspace, workspace_bytes,
-                    stream);
+                                  int64_t *step_counter, float lr, const float *feat, const float *target, int64_t n,
+                                  float *grad_out, void *workspace, size_t workspace_bytes, void *stream) {
+  return train_step(mlp, master, adam_m, adam_v, step, step_counter, lr, feat, target, n, grad_out, 0, workspace,
+                    workspace_bytes, stream);
 }
 
 sa_status sa_surrogate_train_step_pairwise(const sa_mlp *mlp, float *master, float *adam_m, float *adam_v,
-                                           int64_t step, float lr, const float *feat, const float *log_time,
-                                           int64_t n, int32_t group, float *grad_out, void *workspace,
-                                           size_t workspace_bytes, void *stream) {
+                                           int64_t step, int64_t *step_counter, float lr, const float *feat,
+                                           const float *log_time, int64_t n, int32_t group, float *grad_out,
+                                           void *workspace, size_t workspace_bytes, void *stream) {
   if (group < 2 || group > SA_RANK_GROUP_MAX) return fail(SA_ERR_ARG, "group %d outside [2, %d]", group, SA_RANK_GROUP_MAX);
   if (n % group != 0) return fail(SA_ERR_ARG, "n = %lld is not a multiple of group %d", (long long)n, group);
-  return train_step(mlp, master, adam_m, adam_v, step, lr, feat, log_time, n, grad_out, group, workspace,
-                    workspace_bytes, stream);
+  return train_step(mlp, master, adam_m, adam_v, step, step_counter, lr, feat, log_time, n, grad_out, group,
+                    workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -11,6 +11,9 @@ rocprofv3 collects while `run` launches each case exactly once.
 
   GPU, under rocprofv3 --pmc:  python -m paper_1701_08547_amd.imix run
   any host:                    python -m paper_1701_08547_amd.imix compare --counters X.csv
+  any host:                    python -m paper_1701_08547_amd.imix table --counters X.csv --out T.txt
+                               (the per-dispatch counts as a small text table,
+                               which `compare --table T.txt` reads instead)
 
 Static per-wave counts assume every lane takes the same path and every wave
 runs the same trip counts; the differences the comparison reports are the
@@ -23,6 +26,7 @@ import argparse
 import csv
 import ctypes
 import json
+import re
 import sys
 
 import numpy as np
@@ -101,6 +105,35 @@ def read_counters(path: str) -> list:
     return [disp[k] for k in sorted(disp)]
 
 
+TABLE_FIELDS = ("kernel", "SQ_WAVES") + tuple(COUNTERS)
+
+
+def write_table(dyn: list, path: str):
+    """The measured-family dispatches' counter sums as a text table (one
+    line per dispatch, launch order)."""
+    with open(path, "w") as f:
+        f.write("# " + " ".join(TABLE_FIELDS) + "\n")
+        for d in dyn:
+            m = re.search(r"rt_\w+(<[^>]*>)?", d["kernel"])
+            f.write(" ".join([m.group(0).replace(" ", "") if m else "unknown"] +
+                             ["%d" % int(round(d.get(c, -1))) for c in TABLE_FIELDS[1:]]) + "\n")
+
+
+def read_table(path: str) -> list:
+    out = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            d = {"kernel": parts[0]}
+            for c, v in zip(TABLE_FIELDS[1:], parts[1:]):
+                if int(v) >= 0:
+                    d[c] = float(v)
+            out.append(d)
+    return out
+
+
 def compare(pred: list, dyn: list) -> dict:
     """Error rates (static - dynamic) / dynamic per case and class; mean
     absolute error per family and class."""
@@ -133,8 +166,9 @@ def compare(pred: list, dyn: list) -> dict:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=("run", "compare"))
+    ap.add_argument("what", choices=("run", "compare", "table"))
     ap.add_argument("--counters", help="rocprofv3 counter-collection CSV of a `run`")
+    ap.add_argument("--table", help="per-dispatch text table written by `table` (instead of --counters)")
     ap.add_argument("--n-cu", type=int, default=256)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -143,7 +177,11 @@ def main(argv=None):
         n_cu = run(cs)
         print(json.dumps({"cases": len(cs), "n_cu": n_cu}), flush=True)
         return 0
-    rep = compare(predicted(cs, a.n_cu), read_counters(a.counters))
+    if a.what == "table":
+        write_table(read_counters(a.counters), a.out)
+        return 0
+    dyn = read_table(a.table) if a.table else read_counters(a.counters)
+    rep = compare(predicted(cs, a.n_cu), dyn)
     txt = json.dumps(rep, indent=1)
     if a.out:
         with open(a.out, "w") as f:

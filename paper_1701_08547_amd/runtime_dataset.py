@@ -155,6 +155,49 @@ def measure(instances, n_cu: int, device="cuda", warmup: int = 1, reps: int = 10
     return out
 
 
+class Timer:
+    """The timing harness on device buffers sized for a set of instances:
+    time(fam, n, T, U) runs the paper's protocol (one warm-up launch, ten
+    timed launches, the fifth smallest kept; Sec. IV-A) on the given
+    configurations only and returns their milliseconds and the wall-clock
+    seconds the whole measurement took (launches, events and the host's
+    waits included): the cost an empirical search pays for them."""
+
+    def __init__(self, instances, n_cu: int, device="cuda", seed: int = 0):
+        import torch
+
+        self.n_cu, self.device = n_cu, device
+        gen = torch.Generator(device=device)
+        gen.manual_seed(170108547 + int(seed))
+        L = _lib()
+        self.bufs = {}
+        for fam in FAMILIES:
+            sizes = [n for f, n in instances if f == fam]
+            if sizes:
+                self.bufs[fam] = [torch.randn(m, generator=gen, device=device) if m else None
+                                  for m in (int(L.sa_rt_buffer_floats(FAMILY_ID[fam], max(sizes), w))
+                                            for w in range(3))]
+        torch.cuda.synchronize(device)
+
+    def time(self, fam: str, n: int, T, U, warmup: int = 1, reps: int = 10, keep: int = 5):
+        import torch
+
+        T = np.ascontiguousarray(T, dtype=np.int32)
+        U = np.ascontiguousarray(U, dtype=np.int32)
+        ms = np.zeros(T.size, np.float32)
+        a, b, c = self.bufs[fam]
+        p = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        t0 = time.perf_counter()
+        st = _lib().sa_rt_measure(FAMILY_ID[fam], n, p(a), p(b), p(c), T.ctypes.data_as(ctypes.c_void_p),
+                                  U.ctypes.data_as(ctypes.c_void_p), int(T.size), self.n_cu, warmup, reps, keep,
+                                  ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(stream))
+        wall = time.perf_counter() - t0
+        if st != 0:
+            raise RuntimeError("sa_rt_measure: %s" % _lib().sa_rt_last_error().decode())
+        return ms, wall
+
+
 def build(per_family: int, seed: int = 0, device="cuda", log=None) -> dict:
     import torch
 

@@ -232,9 +232,22 @@ def test_product_division_bound():
 def test_pairwise_train_argument_errors(L):
     m = api.SaMlp(*([ctypes.c_void_p(256)] * 8))
     p = ctypes.c_void_p(256)
-    call = lambda n, group: L.sa_surrogate_train_step_pairwise(ctypes.byref(m), p, p, p, 1, ctypes.c_float(1e-3), p, p,
-                                                               n, group, None, p, 1 << 30, None)
+    call = lambda n, group: L.sa_surrogate_train_step_pairwise(ctypes.byref(m), p, p, p, 1, None, ctypes.c_float(1e-3),
+                                                               p, p, n, group, None, p, 1 << 30, None)
     assert call(256, 1) == -1           # group below 2
     assert call(2048, 2048) == -1       # group above the maximum
     assert call(300, 128) == -1         # n not a multiple of the group
     assert b"group" in L.sa_last_error() or b"multiple" in L.sa_last_error()
+
+
+def test_train_step_counter_arguments(L):
+    """A host step number and a device step counter are exclusive; the
+    counter must be 8-byte aligned.  Checked before any launch."""
+    m = api.SaMlp(*([ctypes.c_void_p(256)] * 8))
+    p = ctypes.c_void_p(256)
+    call = lambda step, counter: L.sa_surrogate_train_step(ctypes.byref(m), p, p, p, step, counter,
+                                                           ctypes.c_float(1e-3), p, p, 64, None, p, 1 << 30, None)
+    assert call(0, None) == -1                        # no step number and no counter
+    assert call(3, ctypes.c_void_p(4096)) == -1       # both
+    assert call(0, ctypes.c_void_p(4100)) == -2       # counter misaligned
+    assert b"step" in L.sa_last_error() or b"aligned" in L.sa_last_error()

@@ -340,3 +340,57 @@ def test_training_and_inference_forward_agree():
     say("train/infer gap: rms %.3g mean %.3g (rms Delta %.3g)" % (mse_gap ** 0.5, mean_gap, rms_delta))
     assert mse_gap ** 0.5 <= 2 ** -9 * (1.0 + rms_delta)
     assert abs(mean_gap) <= 2 ** -10 * (1.0 + rms_delta)
+
+
+def test_graph_captured_epochs_equal_eager_steps():
+    """correction.train with each epoch's steps captured in one HIP graph
+    (Adam's step number from the device counter) leaves the same weights, the
+    same Adam moments and the same losses as the same steps issued one by
+    one with host step numbers; squared error and the pairwise loss."""
+    from paper_1701_08547_amd import correction
+
+    arch = oracle.arch_cdna4()
+    b = feature_batch(77, [30000])
+    f = oracle_features(b, arch)[legal_mask(b, arch)][:9216]
+    assert f.shape[0] == 9216
+    mean, inv = norm_stats(f)
+    g = np.random.default_rng(8)
+    ft = torch.from_numpy(f).cuda()
+    for group in (0, 64):
+        tgt = (0.3 * np.tanh(f[:, 22] - f[:, 22].mean()) + 0.05 * g.standard_normal(f.shape[0])).astype(np.float32)
+        tt = torch.from_numpy(tgt).cuda()
+        runs = {}
+        for graph in (False, True):
+            say("train epochs, group", group, "graph", graph)
+            sur, losses = correction.train(ft, tt, mean, inv, epochs=3, batch=2048, lr=2e-3, seed=5, group=group,
+                                           graph=graph)
+            torch.cuda.synchronize()
+            runs[graph] = (sur.master.cpu().numpy(), sur.m.cpu().numpy(), sur.v.cpu().numpy(), losses,
+                           sur.step_count, int(sur.steps_dev.item()) if graph else None)
+        e, c = runs[False], runs[True]
+        assert e[4] == c[4] == 3 * 4 and c[5] == 12
+        for i in range(3):
+            assert np.array_equal(e[i].view(np.uint32), c[i].view(np.uint32)), (group, i)
+        assert e[3] == c[3]
+
+
+def test_training_step_speed():
+    """A 4,096-row step inside a captured epoch (the training loop's
+    configuration) takes well under 100 us; the figure is printed."""
+    from paper_1701_08547_amd import correction
+
+    n, batch = 1 << 18, 4096
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    ft = torch.randn((n, 24), generator=g, device="cuda")
+    tt = torch.randn(n, generator=g, device="cuda") * 0.1
+    correction.train(ft, tt, np.zeros(24, np.float32), np.ones(24, np.float32), epochs=1, batch=batch)
+    torch.cuda.synchronize()
+    import time
+
+    t0 = time.perf_counter()
+    correction.train(ft, tt, np.zeros(24, np.float32), np.ones(24, np.float32), epochs=3, batch=batch)
+    torch.cuda.synchronize()
+    per_step = (time.perf_counter() - t0) / (3 * n // batch)
+    say("training: %.1f us per %d-row step (3 epochs, wall clock incl. capture and shuffles)" % (per_step * 1e6, batch))
+    assert per_step < 1e-4

@@ -88,3 +88,29 @@ def test_streamed_graph_replay_matches_eager():
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(st.idx, eager[0]) and torch.equal(st.val.view(torch.int32), eager[1].view(torch.int32))
+
+
+def test_c4_recipe_sampled():
+    """The 100,000-variant streamed batch itself (1.26e10 evaluations, rows
+    generated on the device per chunk, top-16, plain keys): the top-16 rows of
+    1,000 seeded variants and of the 20 largest ones equal the oracle's on rows
+    rebuilt by the CPU replica of the generator."""
+    arch = oracle.arch_cdna4()
+    b = workloads.c4(n_cu=arch["n_cu"])
+    say("c4 n_evals", b.n_evals)
+    st = streamed.Streamed(b, arch, k=16, chunk_evals=1 << 28, surrogate=None)
+    st.run(corrected=False)
+    torch.cuda.synchronize()
+    idx, val = st.idx.cpu().numpy(), st.val.cpu().numpy()
+    del st
+    torch.cuda.empty_cache()
+    sizes = b.seg[1:] - b.seg[:-1]
+    g = np.random.default_rng(170108547)
+    pick = np.unique(np.concatenate([g.choice(b.n_var, 1000, replace=False), np.argsort(sizes)[-20:]]))
+    for part in np.array_split(pick, 8):
+        sub = b.subset(part)
+        say("c4 oracle part", len(part), sub.n_evals)
+        ref = oracle.run(arch, sub.variants, sub.configs(), k=16, want_occ=False, want_f64=False)
+        assert np.array_equal(idx[part], ref["idx"])
+        assert np.array_equal(val[part].view(np.uint32), ref["val"].view(np.uint32))
+    assert np.all(idx[:, 0] >= 0)
