@@ -66,11 +66,19 @@ typedef int32_t sa_status;
  *
  * Occupancy of a launch with T threads, R registers per thread and S bytes of
  * LDS per block (W_B = ceil(T / wave_size) waves per block):
- *   G_W = min(B_lim, floor(max_waves_per_cu / W_B))         (Eq. 3)
+ *   P = simd_per_cu partitions; a block of W_B waves is admitted by
+ *   partitions with w free wave places each:
+ *     f(w) = floor(P w / W_B)                 when W_B <= P (one wave per
+ *                                             partition: the places pool),
+ *     f(w) = floor(P (w - c) / W_B) + 1       when W_B > P and w >= c,
+ *            c = ceil(W_B / P) (every partition needs c free places and the
+ *            waves go round-robin), 0 when w < c;
+ *   with P = 1 both are the pooled floor(w / W_B).
+ *   G_W = min(B_lim, f(max_waves_per_cu / P))                (Eq. 3)
  *         B_lim = max_blocks_per_cu, unlimited when W_B = 1 and
  *         single_wave_exempt != 0
- *   G_R = floor(simd_per_cu * w_v / W_B),                    (Eq. 4, plain reading)
- *         w_v = min(max_waves_per_cu / simd_per_cu,
+ *   G_R = f(w_v),                                            (Eq. 4, plain reading)
+ *         w_v = min(max_waves_per_cu / P,
  *                   floor(vgprs_per_simd_lane / roundup(R, vgpr_granule)));
  *         unlimited when R = 0
  *   G_S = floor(lds_per_cu / roundup(S, lds_granule)),       (Eq. 5, floor)
@@ -83,7 +91,7 @@ typedef int32_t sa_status;
  * Supported ranges (sa_arch_validate): wave_size a power of two in [2, 1024];
  * max_threads_per_block in [1, 65536], a multiple of wave_size, with
  * max_threads_per_block / wave_size <= 64; max_waves_per_cu in [1, 64];
- * simd_per_cu in [1, max_waves_per_cu]; max_blocks_per_cu >= 1; vgpr_granule
+ * simd_per_cu a power of two in [1, max_waves_per_cu]; max_blocks_per_cu >= 1; vgpr_granule
  * a power of two dividing max_vgprs_per_thread, with
  * (max_vgprs_per_thread / vgpr_granule + 2) x
  * (max_threads_per_block / wave_size + 2) <= 16384;
@@ -190,9 +198,11 @@ const char *sa_last_error(void);
 
 /* CDNA4 / MI355X constants without any device query (n_cu = 256): wave 64,
  * 32 wave slots over 4 SIMDs, 512 unified VGPR/AGPR per SIMD lane (granule
- * 8), 160 KiB LDS per CU (granule 512 B), 16 multi-wave blocks per CU,
- * w_sat 32, U <= 64, G <= 2^18, CPI 2^-6 (fp, int), 2^-4 (memory, branch,
- * barrier), 2^-5 (register moves).  Fills *out; SA_ERR_ARG if out is NULL. */
+ * 8), 160 KiB LDS per CU (granule 1,280 B), 16 multi-wave blocks per CU
+ * (one-wave blocks exempt), w_sat 32, U <= 64, G <= 2^18, CPI 2^-6 (fp,
+ * int), 2^-4 (memory, branch, barrier), 2^-5 (register moves).  The
+ * occupancy constants are the ones sa_rt_residency measures on the device.
+ * Fills *out; SA_ERR_ARG if out is NULL. */
 sa_status sa_arch_gfx950(sa_arch *out);
 
 /* The same, with n_cu, wave size, thread and LDS limits read from HIP device

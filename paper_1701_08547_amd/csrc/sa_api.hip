@@ -64,6 +64,7 @@ sa_status check_arch(const sa_arch *a) {
 #undef SA_RANGE
   if (!pow2(a->wave_size)) return fail(SA_ERR_UNSUPPORTED, "wave_size %d is not a power of two", a->wave_size);
   if (!pow2(a->vgpr_granule)) return fail(SA_ERR_UNSUPPORTED, "vgpr_granule %d is not a power of two", a->vgpr_granule);
+  if (!pow2(a->simd_per_cu)) return fail(SA_ERR_UNSUPPORTED, "simd_per_cu %d is not a power of two", a->simd_per_cu);
   if (a->max_threads_per_block % a->wave_size)
     return fail(SA_ERR_UNSUPPORTED, "max_threads_per_block %d is not a multiple of wave_size %d",
                 a->max_threads_per_block, a->wave_size);
@@ -110,6 +111,7 @@ sa::KArch to_karch(const sa_arch *a) {
   k.nr = (int32_t)ceil_div(a->max_vgprs_per_thread, a->vgpr_granule);
   k.ws_shift = log2_exact(a->wave_size);
   k.gran_shift = log2_exact(a->vgpr_granule);
+  k.simd_shift = log2_exact(a->simd_per_cu);
   return k;
 }
 

@@ -344,11 +344,10 @@ __device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, co
   B = B < pc.gs ? B : pc.gs;
   B = ok ? B : 0;
   const int32_t W = __umul24(B, WB);
-  (void)mwb;
-  const int32_t gwv = blocks_on_partitions(A.max_waves / A.simd, WB, A.simd);
+  const int32_t gwv = blocks_on_partitions_m(A.max_waves >> A.simd_shift, WB, A.simd_shift, mwb[WB]);
   t.WB = WB;
   t.gw = gwv < (int32_t)blim[WB] ? gwv : (int32_t)blim[WB];
-  t.gr = rg == 0 ? kUnlimited : blocks_on_partitions(wsimd[rg], WB, A.simd);
+  t.gr = rg == 0 ? kUnlimited : blocks_on_partitions_m(wsimd[rg], WB, A.simd_shift, mwb[WB]);
   t.gs = pc.gs;
   t.B = B;
   t.W = W;
@@ -449,7 +448,7 @@ __device__ void build_tables(const EvalLaunch &L, uint8_t *dyn_lds, float *tab_r
     const int rg = i / row, wb = i - rg * row;
     uint32_t b = 0;
     if (wb >= 1) {
-      b = (uint32_t)blocks_on_partitions(tab_wsimd[rg], wb, A.simd);
+      b = (uint32_t)blocks_on_partitions_m(tab_wsimd[rg], wb, A.simd_shift, tab_mwb[wb]);
       b = b < tab_blim[wb] ? b : tab_blim[wb];
     }
     tab_b[i] = (uint8_t)b;

@@ -32,6 +32,16 @@ __host__ __device__ inline int32_t blocks_on_partitions(int32_t w, int32_t WB, i
   return w >= c ? simd * (w - c) / WB + 1 : 0;
 }
 
+// The same without a division: simd = 2^simd_shift, mwb = ceil(2^16 / WB)
+// (floor(x mwb / 2^16) = floor(x / WB) for x < 1024, and x <= simd x max
+// waves per partition stays below that).
+__host__ __device__ inline int32_t blocks_on_partitions_m(int32_t w, int32_t WB, int32_t simd_shift, uint32_t mwb) {
+  const int32_t simd = 1 << simd_shift;
+  if (WB <= simd) return (int32_t)(((uint32_t)(w << simd_shift) * mwb) >> 16);
+  const int32_t c = (WB + simd - 1) >> simd_shift;
+  return w >= c ? (int32_t)(((uint32_t)((w - c) << simd_shift) * mwb) >> 16) + 1 : 0;
+}
+
 // Descriptor as the kernels read it: the public fields plus the sizes and
 // division constants the host derives from them once per call.
 struct KArch {
@@ -42,6 +52,7 @@ struct KArch {
   int32_t nr;      // ceil(max_vgprs / vgpr_gran): largest register granule count
   int32_t ws_shift;    // log2(ws)         (wave size is a power of two)
   int32_t gran_shift;  // log2(vgpr_gran)  (register granule is a power of two)
+  int32_t simd_shift;  // log2(simd)       (partition count is a power of two)
 };
 
 struct KVariants {

@@ -195,12 +195,16 @@ __global__ __launch_bounds__(kTrainThreads) void sa_train_kernel(MlpDev M, const
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
   const int r = lane & 15, q = lane >> 4;
   load_weights_t(M, s.f, tid, kTrainThreads);
-  for (int i = tid; i < kMH * kMH; i += kTrainThreads) {
-    const int k = i / kMH, p = i % kMH;
-    s.W2b[k * kLdW2 + p] = M.W2[w2_column(p) * kMH + k];
-  }
   for (int i = tid; i < kMH; i += kTrainThreads) s.w3[i] = bf2f(M.w3[i]);
   if (step_counter && blockIdx.x == 0 && tid == 0) *step_counter += 1;  // read by the update kernel
+  __syncthreads();
+  // the backward's W2 from the forward's staged copy (64 W2, columns permuted):
+  // W2b[k][p] = W2[w2_column(p)][k] = staged[w2_column(p)][w2_position(k)] / 64
+  for (int i = tid; i < kMH * kMH; i += kTrainThreads) {
+    const int k = i / kMH, p = i % kMH;
+    const float v = bf2f(s.f.W2[w2_column(p) * kLdW2 + w2_position(k)]) * (1.0f / kTScale);
+    s.W2b[k * kLdW2 + p] = (uint16_t)(__float_as_uint(v) >> 16);
+  }
   __syncthreads();
   const float inv_n2 = 2.0f / (float)n;
   // per-lane running sums over this workgroup's rows (reduced at the end)
@@ -453,22 +457,40 @@ __global__ __launch_bounds__(256) void sa_train_rank_kernel(const float *feat, c
 }
 
 // Sum the workgroups' partials (fixed order: deterministic), then Adam on the
-// fp32 master weights and the bf16 shadow.  One thread per parameter.  With
-// a step counter, the bias corrections follow the count the training kernel
-// has just advanced.
-__global__ void sa_train_adam_kernel(TrainState S, MlpDev Mw, const float *part, int64_t n_parts, AdamArgs h,
-                                     float *grad_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kPartStride) return;
+// fp32 master weights and the bf16 shadow.  A workgroup takes 64 parameters:
+// each of its four waves adds every fourth partial (4 loads in flight per
+// lane), and the four sums are added in wave order.  With a step counter,
+// the bias corrections follow the count the training kernel has just
+// advanced.
+constexpr int kAdamParams = 64;
+
+__global__ __launch_bounds__(256) void sa_train_adam_kernel(TrainState S, MlpDev Mw, const float *part,
+                                                            int64_t n_parts, AdamArgs h, float *grad_out) {
+  __shared__ float red[4][kAdamParams];
+  const int j = threadIdx.x & (kAdamParams - 1), wv = threadIdx.x / kAdamParams;
+  const int64_t i = (int64_t)blockIdx.x * kAdamParams + j;
   float g = 0.0f;
-  for (int64_t p = 0; p < n_parts; ++p) g += part[p * kPartStride + i];
+  if (i < kPartStride) {
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int64_t p = wv;
+    for (; p + 12 < n_parts; p += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += part[(p + 4 * u) * kPartStride + i];
+    }
+    for (; p < n_parts; p += 4) acc[0] += part[p * kPartStride + i];
+    g = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+  red[wv][j] = g;
+  __syncthreads();
+  if (wv != 0 || i >= kPartStride) return;
+  g = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
   if (grad_out) grad_out[i] = i == kPartLoss ? g * h.inv_n : g;
   if (i >= kPartUsed) return;
   float bc1 = h.bc1, bc2 = h.bc2;
   if (h.step_counter) {
     const double t = (double)*h.step_counter;
-    bc1 = (float)(1.0 - pow((double)h.beta1, t));
-    bc2 = (float)(1.0 - pow((double)h.beta2, t));
+    bc1 = (float)(1.0 - pow(h.beta1_d, t));
+    bc2 = (float)(1.0 - pow(h.beta2_d, t));
   }
   const float m = h.beta1 * S.m[i] + (1.0f - h.beta1) * g;
   const float v = h.beta2 * S.v[i] + (1.0f - h.beta2) * g * g;
@@ -480,9 +502,9 @@ __global__ void sa_train_adam_kernel(TrainState S, MlpDev Mw, const float *part,
   uint16_t *W1 = (uint16_t *)Mw.W1, *W2 = (uint16_t *)Mw.W2, *w3 = (uint16_t *)Mw.w3;
   float *b1 = (float *)Mw.b1, *b2 = (float *)Mw.b2, *b3 = (float *)Mw.b3;
   if (i < kPartW1 + kMH * kMK && i >= kPartW1) {
-    const int64_t j = i - kPartW1;
-    W1[j] = (j % kMK) < kF ? f2bf(p) : 0;  // padding inputs stay zero
-    if ((j % kMK) >= kF) S.master[i] = 0.0f;
+    const int64_t jw = i - kPartW1;
+    W1[jw] = (jw % kMK) < kF ? f2bf(p) : 0;  // padding inputs stay zero
+    if ((jw % kMK) >= kF) S.master[i] = 0.0f;
   } else if (i >= kPartW2 && i < kPartW2 + kMH * kMH) {
     W2[i - kPartW2] = f2bf(p);
   } else if (i >= kPartW3 && i < kPartW3 + kMH) {
@@ -540,8 +562,8 @@ hipError_t launch_train_step(const MlpDev &M, TrainState S, const float *feat, c
                        h.step_counter);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(sa_train_adam_kernel, dim3((uint32_t)((kPartStride + 255) / 256)), dim3(256), 0, stream, S, M,
-                     T.part, parts, h, grad_out);
+  hipLaunchKernelGGL(sa_train_adam_kernel, dim3((uint32_t)((kPartStride + kAdamParams - 1) / kAdamParams)), dim3(256),
+                     0, stream, S, M, T.part, parts, h, grad_out);
   return hipGetLastError();
 }
 

@@ -141,8 +141,10 @@ sa_status train_step(const sa_mlp *mlp, float *master, float *adam_m, float *ada
   h.beta1 = 0.9f;
   h.beta2 = 0.999f;
   h.eps = 1e-8f;
-  h.bc1 = step > 0 ? (float)(1.0 - pow(0.9, (double)step)) : 1.0f;
-  h.bc2 = step > 0 ? (float)(1.0 - pow(0.999, (double)step)) : 1.0f;
+  h.beta1_d = 0.9;
+  h.beta2_d = 0.999;
+  h.bc1 = step > 0 ? (float)(1.0 - pow(h.beta1_d, (double)step)) : 1.0f;
+  h.bc2 = step > 0 ? (float)(1.0 - pow(h.beta2_d, (double)step)) : 1.0f;
   h.step_counter = step_counter;
   // the ranking loss's per-row terms already carry its normalisation
   h.inv_n = group > 0 ? 1.0f : 1.0f / (float)n;

@@ -174,6 +174,12 @@ __device__ __forceinline__ int w2_column(int p) {
   return 32 * c + (j < 4 ? 4 * q + j : 12 + 4 * q + j);
 }
 
+// Position of hidden unit u in a permuted row: the inverse of w2_column.
+__device__ __forceinline__ int w2_position(int u) {
+  const int c = u >> 5, m = u & 31;
+  return m < 16 ? 32 * c + 8 * (m >> 2) + (m & 3) : 32 * c + 8 * ((m - 16) >> 2) + 4 + (m & 3);
+}
+
 // bfloat16 bits times 64 (exact: only the exponent changes; zero stays zero).
 __device__ __forceinline__ uint16_t bf16_x64(uint16_t b) {
   const float x = __builtin_bit_cast(float, (uint32_t)b << 16) * kTScale;
@@ -278,44 +284,65 @@ __device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, i
       const u32x4_t x = *(const u32x4_t *)(X + (16 * (2 * p + i) + r) * kLdXin + 8 * qx);
       xb[i] = q == 3 ? u32x4_t{0u, 0u, 0u, 0u} : ((SHARED && q == 0) ? xv : x);
     }
-    // layer 1: hidden tile t -> two row tiles x 4 packed bf16 (two dwords)
+    // layer 1: hidden tile t -> two row tiles x 4 packed bf16 (two dwords).
+    // Software-pipelined: tile t + 1's MFMAs are issued before tile t's GELU,
+    // so that the matrix cores work while the vector unit does the table GELU.
     uint32_t h1[8][2][2];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    auto l1 = [&](int t, f32x4_t (&d)[2]) {
       const u32x4_t a = *(const u32x4_t *)(s.W1 + (16 * t + r) * kLdW1 + 8 * q);
       const f32x4_t bias = *(const f32x4_t *)(s.b1 + 16 * t + 4 * q);
-      const f32x4_t d[2] = {mfma32(a, xb[0], bias), mfma32(a, xb[1], bias)};
-      gelu_pack(d, s.gelu, h1[t]);
+      d[0] = mfma32(a, xb[0], bias);
+      d[1] = mfma32(a, xb[1], bias);
+    };
+    f32x4_t d_cur[2], d_nxt[2];
+    l1(0, d_cur);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (t < 7) l1(t + 1, d_nxt);
+      gelu_pack(d_cur, s.gelu, h1[t]);
+      if (t < 7) {
+        d_cur[0] = d_nxt[0];
+        d_cur[1] = d_nxt[1];
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
-    // layers 2 and 3, one 32-unit chunk of the second hidden layer at a time
-    f32x4_t acc3[2] = {f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}, f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}};
-#pragma unroll 1
-    for (int c3 = 0; c3 < 4; ++c3) {
-      uint32_t h2[2][2][2];
+    // layers 2 and 3, pipelined the same way over the 8 output tiles; each
+    // pair of tiles (a 32-unit chunk) feeds the third layer at once
+    auto l2 = [&](int ot, f32x4_t (&acc)[2]) {
+      const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
+      acc[0] = bias;
+      acc[1] = bias;
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int ot = 2 * c3 + half;
-        const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
-        f32x4_t acc[2] = {bias, bias};
+      for (int c = 0; c < 4; ++c) {
+        const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const u32x4_t b = {h1[2 * c][i][0], h1[2 * c][i][1], h1[2 * c + 1][i][0], h1[2 * c + 1][i][1]};
-            acc[i] = mfma32(a, b, acc[i]);
-          }
+        for (int i = 0; i < 2; ++i) {
+          const u32x4_t b = {h1[2 * c][i][0], h1[2 * c][i][1], h1[2 * c + 1][i][0], h1[2 * c + 1][i][1]};
+          acc[i] = mfma32(a, b, acc[i]);
         }
-        gelu_pack(acc, s.gelu, h2[half]);
-        __builtin_amdgcn_sched_barrier(0);
       }
-      const u32x4_t a3 = *(const u32x4_t *)(s.w3p + 32 * c3 + 8 * q);
+    };
+    f32x4_t acc3[2] = {f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}, f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}};
+    f32x4_t a_cur[2], a_nxt[2];
+    uint32_t h2[2][2][2];
+    l2(0, a_cur);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const u32x4_t b = {h2[0][i][0], h2[0][i][1], h2[1][i][0], h2[1][i][1]};
-        acc3[i] = mfma32(a3, b, acc3[i]);
+    for (int ot = 0; ot < 8; ++ot) {
+      if (ot < 7) l2(ot + 1, a_nxt);
+      gelu_pack(a_cur, s.gelu, h2[ot & 1]);
+      if (ot & 1) {
+        const u32x4_t a3 = *(const u32x4_t *)(s.w3p + 32 * (ot >> 1) + 8 * q);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const u32x4_t b = {h2[0][i][0], h2[0][i][1], h2[1][i][0], h2[1][i][1]};
+          acc3[i] = mfma32(a3, b, acc3[i]);
+        }
       }
+      if (ot < 7) {
+        a_cur[0] = a_nxt[0];
+        a_cur[1] = a_nxt[1];
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     // lane l = 16 q + r owns row l, which is row r of row tile q
     delta = q == 2 * p ? acc3[0][0] : delta;

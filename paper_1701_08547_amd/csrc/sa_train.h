@@ -33,11 +33,13 @@ struct TrainState {
 };
 
 // Adam's constants; the bias corrections 1 - beta^t come either from the host
-// (step > 0) or from the device counter *step_counter, which the update
-// increments (for steps replayed from a captured graph).
+// (step > 0) or from the device counter *step_counter, which the training
+// kernel advances before the update reads it (steps replayed from a captured
+// graph).
 struct AdamArgs {
   float lr, beta1, beta2, eps, bc1, bc2;
   float inv_n;            // scale of the summed loss entry
+  double beta1_d, beta2_d;  // the betas in binary64, for 1 - beta^t as the host computes it
   int64_t *step_counter;  // nullable
 };
 
