@@ -619,7 +619,9 @@ def regret_leg(per_family: int):
     """Top-1 regret against measured runtimes: a small measured dataset of the
     library's kernel families (the paper's timing protocol), the correction
     trained on three quarters of each family's instances and evaluated on the
-    rest; the same with each family left out of training entirely; and the
+    rest; two ablations on the same split (the network's ranking alone, with
+    and without the features computed from the static model's terms); the
+    same with each family left out of training entirely; and the
     model-guided search run live on the held-out instances (the full sweep and
     the 8 survivors of each key timed again, wall clock compared)."""
     from paper_1701_08547_amd import correction, runtime_dataset
@@ -635,6 +637,17 @@ def regret_leg(per_family: int):
            "paper_pruned_fraction": a.get("pruned_fraction"),
            "regret_paper_pruned_plain": a.get("regret_pruned_plain"),
            "regret_paper_pruned_best": a.get("regret_pruned_best")}
+    # does the static model carry the corrected key?  The same split, the
+    # network ranking alone (trained on the centred log runtime), with and
+    # without the features computed from the model's terms
+    out["ablation"] = {}
+    for name, kw in (("network_alone", {"key": "direct"}),
+                     ("network_alone_without_model_features", {"key": "direct",
+                                                               "drop": correction.MODEL_FEATURES})):
+        _, ra = correction.run(data, epochs=150, seed=7, held_frac=0.25, **kw)
+        out["ablation"][name] = {"regret": ra["all"]["regret_corrected"],
+                                 "regret_ci": ra["all"]["regret_corrected_ci"],
+                                 "spearman": ra["all"]["spearman_corrected"]}
     out["leave_one_family_out"] = correction.leave_one_family_out(data, epochs=150, seed=7)
     out["live_search_k8"] = correction.live_search(data, rep["keys"], k=8)
     out["seconds"] = time.perf_counter() - t0
@@ -681,7 +694,7 @@ def corrected_leg(arch, var, cfg, n_var, n_evals, sur, steps: int) -> dict:
                          "frac": tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                          "note": "39,168 algorithmic FLOP per evaluation (24->128->128->1; the padding of the inputs "
                                  "to 32 is not counted); "
-                                 "bound by vector issue, not by the matrix cores: the table GELU between the layers is three quarters of the vector instructions, and a SIMD issues for about 86 % of the launch (SQ counters)"}}
+                                 "bound by LDS reads first (the GELU table and the weight tiles, about 257 KiB per 64 evaluations), vector issue second; the matrix cores are about a third busy (SQ counters)"}}
 
 
 if __name__ == "__main__":

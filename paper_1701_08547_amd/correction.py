@@ -291,12 +291,22 @@ def evaluate(ms: np.ndarray, ln_s: np.ndarray, z: np.ndarray, held: np.ndarray, 
     return rep
 
 
+# features computed from the static model's terms (occupancy bounds, W_B, B*,
+# W*, E', F and ln score): zeroed by the ablation without the model
+MODEL_FEATURES = (13, 14, 15, 16, 17, 18, 20, 21, 22)
+
+
 def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed: int = 0, device="cuda", log=None,
-        loss: str = "mse", held_frac: float = 0.1, split=None):
+        loss: str = "mse", held_frac: float = 0.1, split=None, key: str = "residual", drop=()):
     """Train on the training instances, evaluate on the held-out ones
     (`held_frac` of each family, or the explicit (train, held) instance
     split).  Returns the Surrogate and the report; the report's "keys" entry
-    holds the held-out instances and their plain and corrected keys."""
+    holds the held-out instances and their plain and corrected keys.
+
+    Ablations: key="direct" trains the network on the centred log runtime
+    itself and ranks by Delta alone (no ln score term in the key); `drop`
+    lists feature indices the network does not see (their normalisation
+    scale set to zero, so the input is zero on every row)."""
     import torch
 
     n_inst = int(data["instance"].max()) + 1
@@ -308,7 +318,14 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     legal = np.isfinite(ln_s)
     if not legal.all():
         raise ValueError("%d configurations are illegal under the model" % int((~legal).sum()))
-    r = residual_targets(np.log(ms), ln_s)
+    if key == "residual":
+        r = residual_targets(np.log(ms), ln_s)
+    elif key == "direct":
+        if loss != "mse":
+            raise ValueError("the direct key is trained on the squared error only")
+        r = np.log(ms) - np.median(np.log(ms), axis=1, keepdims=True)
+    else:
+        raise ValueError("key must be 'residual' or 'direct'")
     families = data["family"].reshape(n_inst, N_CFG)[:, 0]
     tr, held = holdout_split(families, held_frac, seed) if split is None else (np.asarray(split[0]),
                                                                                  np.asarray(split[1]))
@@ -317,6 +334,8 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     mean = f_np[rows_tr].mean(0).astype(np.float32)
     sd = f_np[rows_tr].std(0)
     inv = np.where(sd > 1e-12, 1.0 / np.maximum(sd, 1e-12), 1.0).astype(np.float32)
+    for j in drop:
+        mean[j], inv[j] = 0.0, 0.0
     idx = torch.from_numpy(rows_tr).to(device)
     f_tr = feat.index_select(0, idx).contiguous()
     if loss == "pairwise":
@@ -332,7 +351,8 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     sur, losses = train(f_tr, r_tr, mean, inv, epochs, batch, lr, seed, device, log, group=group)
     torch.cuda.synchronize()
     train_s = time.time() - t0
-    z = corrected_keys(feat, sur).cpu().numpy().astype(np.float64).reshape(n_inst, N_CFG)
+    zt = corrected_keys(feat, sur) if key == "residual" else sur.forward(feat)
+    z = zt.cpu().numpy().astype(np.float64).reshape(n_inst, N_CFG)
     kept = api.suggest(arch, var).cpu().numpy().view(np.uint64)
     ws = int(arch["wave_size"])
     T = data["block"].astype(np.int64)
@@ -340,7 +360,7 @@ def run(data: dict, epochs: int = 40, batch: int = 4096, lr: float = 1e-3, seed:
     pruned = ((T % ws == 0) & (((kept >> j) & np.uint64(1)) == 1)).reshape(n_inst, N_CFG)
     rep = evaluate(ms, ln_s, z, held, families, pruned)
     rep["keys"] = {"held": held, "plain": ln_s[held], "corrected": z[held]}
-    rep["train"] = {"loss": loss, "rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
+    rep["train"] = {"loss": loss, "key": key, "dropped_features": [int(j) for j in drop], "rows": int(rows_tr.size), "epochs": epochs, "batch": batch, "lr": lr, "seconds": train_s,
                     "loss_first": losses[0], "loss_last": losses[-1],
                     "target_var": float(np.var(r.reshape(-1)[rows_tr]))}
     return sur, rep

@@ -11,6 +11,7 @@
 
 #include "sa.h"
 #include "sa_internal.h"
+#include "sa_corrected.h"
 
 namespace {
 thread_local char g_err[512] = "";
@@ -142,9 +143,10 @@ size_t frag_bytes(int64_t n_evals, int32_t tile, int32_t k) {
   return (size_t)(2 * tiles * (int64_t)k * (int64_t)sizeof(uint64_t));
 }
 
-// Tile sa_score picks for the plain or the corrected pass.
+// Tile sa_score sizes its workspace for: the plain pass's, or for the
+// corrected pass (~100x the work per evaluation) the smallest, which bounds
+// the fragment slots of whatever tile its launch then picks.
 int32_t score_tile(int64_t n_evals, bool corrected) {
-  // the corrected pass does ~100x the work per evaluation: smallest tiles
   return corrected ? (g_tile > 0 ? g_tile : sa::kTileMin) : pick_tile(n_evals);
 }
 
@@ -347,11 +349,12 @@ sa_status sa_score(const sa_arch *arch, const sa_variants *variants, const sa_co
   L.topk_idx = topk_idx;
   L.topk_val = topk_val;
   L.k = topk ? k : 0;
-  L.tile = score_tile(n_evals, mlp != nullptr);
-  L.n_tiles = ceil_div(n_evals, L.tile);
   L.need_score = (score || topk) ? 1 : 0;
   L.vec = all16({configs->block, configs->unroll, configs->regs, configs->grid, occ_waves, score}) ? 1 : 0;
   set_lds_layout(L);
+  L.tile = (mlp && g_tile <= 0) ? sa::corrected_tile(n_evals, L.dyn_lds_bytes, configs->grid != nullptr)
+                                : score_tile(n_evals, mlp != nullptr);
+  L.n_tiles = ceil_div(n_evals, L.tile);
   if (topk && n_variants > 0) {
     if ((st = bind_workspace(L, workspace, workspace_bytes)) != SA_OK) return st;
   }

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sa_corrected.h"
 #include "sa_dev.h"
 #include "sa_mlp_dev.h"
 
@@ -23,6 +24,7 @@ namespace {
 
 constexpr int kCorrWaves = 16;
 constexpr int kCorrCap = 256;  // candidate keys per wave: k <= 64 plus one batch of 64, with room to spare
+constexpr int32_t kCorrTileMax = 8192;
 
 template <bool HAS_GRID>
 __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunch L, MlpDev M) {
@@ -128,14 +130,21 @@ int device_cus() {
   return cus;
 }
 
+// Workgroups of sa_corrected_kernel<G> one CU holds with `dyn` bytes of
+// dynamic LDS.
 template <bool G>
-hipError_t launch_corrected_one(const EvalLaunch &L, const MlpDev &M, hipStream_t stream) {
-  const size_t dyn = (size_t)L.dyn_lds_bytes;
+int resident_blocks(size_t dyn) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sa_corrected_kernel<G>, 64 * kCorrWaves, dyn) != hipSuccess ||
       nb < 1)
     nb = 1;
-  int64_t grid = (int64_t)nb * device_cus();
+  return nb;
+}
+
+template <bool G>
+hipError_t launch_corrected_one(const EvalLaunch &L, const MlpDev &M, hipStream_t stream) {
+  const size_t dyn = (size_t)L.dyn_lds_bytes;
+  int64_t grid = (int64_t)resident_blocks<G>(dyn) * device_cus();
   const int64_t need = (L.n_tiles + kCorrWaves - 1) / kCorrWaves;
   if (grid > need) grid = need;
   if (grid < 1) return hipSuccess;
@@ -144,6 +153,19 @@ hipError_t launch_corrected_one(const EvalLaunch &L, const MlpDev &M, hipStream_
 }
 
 }  // namespace
+
+int32_t corrected_tile(int64_t n_evals, int32_t dyn_lds_bytes, bool has_grid) {
+  const size_t dyn = (size_t)dyn_lds_bytes;
+  const int64_t waves =
+      (int64_t)(has_grid ? resident_blocks<true>(dyn) : resident_blocks<false>(dyn)) * device_cus() * kCorrWaves;
+  // evaluations of the most loaded wave when the tiles are dealt round-robin
+  auto most = [&](int64_t tile) { return (((n_evals + tile - 1) / tile + waves - 1) / waves) * tile; };
+  const int64_t base = most(kTileMin);
+  int32_t best = kTileMin;
+  for (int32_t t = 2 * kTileMin; t <= kCorrTileMax; t *= 2)
+    if (most(t) <= base) best = t;
+  return best;
+}
 
 hipError_t launch_corrected(const EvalLaunch &L, const MlpDev &M, bool has_grid, hipStream_t stream) {
   if (L.n_tiles == 0) return hipSuccess;

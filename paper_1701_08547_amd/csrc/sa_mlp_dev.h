@@ -115,41 +115,55 @@ __device__ __forceinline__ void gelu_t_n(float (&t)[N], const f32x2_t *tab) {
 // ---------------------------------------------------------------- features
 
 // The variant's features (binary32): f0-f8, f19 and f23.
+// Natural logarithm by the device's base-2 logarithm (v_log_f32, about one
+// ulp) times ln 2: two instructions where the library's logf takes about
+// twenty, within the features' tolerance for the positive, normal arguments
+// used here.
+__device__ __forceinline__ float dev_ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147182f; }
+
+// ln(1 + n) of a count (1 + n is exact in binary32 below 2^24).
+__device__ __forceinline__ float ln1p_count(int32_t n) { return dev_ln(1.0f + (float)n); }
+
+// The variant's features (binary32): f0-f8, f19 and f23.
 __device__ __forceinline__ void variant_features(float *f, int32_t nfp, int32_t nint, int32_t nld, int32_t nst,
                                                  int32_t nbr, int32_t nbar, int32_t nreg, int32_t S, float d) {
-  f[0] = log1pf((float)nfp);
-  f[1] = log1pf((float)nint);
-  f[2] = log1pf((float)nld);
-  f[3] = log1pf((float)nst);
-  f[4] = log1pf((float)nbr);
-  f[5] = (float)nbar / 4.0f;
-  f[6] = log1pf((float)nreg);
-  f[7] = (float)S / 65536.0f;
+  f[0] = ln1p_count(nfp);
+  f[1] = ln1p_count(nint);
+  f[2] = ln1p_count(nld);
+  f[3] = ln1p_count(nst);
+  f[4] = ln1p_count(nbr);
+  f[5] = (float)nbar * 0.25f;
+  f[6] = ln1p_count(nreg);
+  f[7] = (float)S * (1.0f / 65536.0f);
   f[8] = d;
   const int32_t mem = nld + nst;
   const float inten = (float)nfp / (float)(mem > 1 ? mem : 1);
-  f[19] = log1pf(inten);
+  f[19] = dev_ln(1.0f + inten);
   // decided on the integers: n_fp / m > 4 exactly when n_fp > 4 m
   f[23] = nfp > 4 * (mem > 1 ? mem : 1) ? 1.0f : 0.0f;
 }
 
-// The configuration's features: f9-f18 and f20-f22.
+// The configuration's features: f9-f18 and f20-f22.  Per evaluation, so the
+// logarithms are the device's and the divisions are products with binary32
+// reciprocals (constants, or v_rcp_f32 for 1/F): each within an ulp or two
+// of the correctly rounded value, far inside the features' tolerance, at a
+// tenth of the instructions of the library's logf and IEEE division.
 __device__ __forceinline__ void config_features(float *f, int32_t T, int32_t U, int32_t R, int32_t G, bool has_grid,
                                                 int32_t n_cu, int32_t WB, int32_t gw, int32_t gr, int32_t gs,
                                                 int32_t B, int32_t W, float Ed, float F, float sc) {
-  f[9] = log2f((float)T) / 10.0f;
-  f[10] = (float)(U - 1) / 7.0f;
-  f[11] = (float)R / 512.0f;
-  f[12] = has_grid ? log2f((float)G / (float)n_cu) / 3.0f : 0.0f;
-  f[13] = (float)WB / 16.0f;
-  f[14] = (float)(gw < 32 ? gw : 32) / 32.0f;
-  f[15] = (float)(gr < 32 ? gr : 32) / 32.0f;
-  f[16] = (float)(gs < 32 ? gs : 32) / 32.0f;
-  f[17] = (float)B / 32.0f;
-  f[18] = (float)W / 32.0f;
-  f[20] = logf(Ed);
-  f[21] = 1.0f / F;
-  f[22] = logf(sc);
+  f[9] = __builtin_amdgcn_logf((float)T) * 0.1f;
+  f[10] = (float)(U - 1) * (1.0f / 7.0f);
+  f[11] = (float)R * (1.0f / 512.0f);
+  f[12] = has_grid ? (__builtin_amdgcn_logf((float)G) - __builtin_amdgcn_logf((float)n_cu)) * (1.0f / 3.0f) : 0.0f;
+  f[13] = (float)WB * (1.0f / 16.0f);
+  f[14] = (float)(gw < 32 ? gw : 32) * (1.0f / 32.0f);
+  f[15] = (float)(gr < 32 ? gr : 32) * (1.0f / 32.0f);
+  f[16] = (float)(gs < 32 ? gs : 32) * (1.0f / 32.0f);
+  f[17] = (float)B * (1.0f / 32.0f);
+  f[18] = (float)W * (1.0f / 32.0f);
+  f[20] = dev_ln(Ed);
+  f[21] = __builtin_amdgcn_rcpf(F);
+  f[22] = dev_ln(sc);
 }
 
 // ---------------------------------------------------------------- forward pass
