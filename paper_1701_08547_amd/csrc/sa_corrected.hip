@@ -23,6 +23,7 @@ namespace sa {
 namespace {
 
 constexpr int kCorrWaves = 16;
+constexpr int kCorrRT = 2;  // row tiles per pass of the network
 constexpr int kCorrCap = 256;  // candidate keys per wave: k <= 64 plus one batch of 64, with room to spare
 constexpr int32_t kCorrTileMax = 8192;
 
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunc
         config_features(f, T, U, R, G, HAS_GRID, A.n_cu, t.WB, t.gw, t.gr, t.gs, t.B, t.W, t.Ed, t.F, t.sc);
         put_x_cfg(s, Xw, lane, f, !legal);
         wave_lds_sync();
-        const float delta = mlp_rows<true>(s, Xw, lane, xv);
+        const float delta = mlp_rows<true, kCorrRT>(s, Xw, lane, xv);
         wave_lds_sync();
         const float z = legal ? f[22] + delta : __builtin_huge_valf();
         if (L.score && in) L.score[row] = z;

@@ -123,6 +123,24 @@ __device__ __forceinline__ int32_t udiv_up(int32_t a, int32_t b, float r) {
   return q - (int32_t)(__umul24((uint32_t)q, (uint32_t)b) > (uint32_t)a);
 }
 
+// a / b in binary32 for the grid factor's operands: integers from 0 to 2^31
+// converted to binary32, b > 0 where the quotient is used.  These are the
+// steps of the IEEE division the compiler emits for `a / b` (reciprocal
+// estimate, one refinement, the quotient and two corrections from exact
+// remainders) without its operand scaling and special-value fix-up, which
+// operands in this range never trigger, so the quotient is the same, in
+// eight instructions instead of eleven.
+__device__ __forceinline__ float div_grid(float a, float b) {
+  float y = __builtin_amdgcn_rcpf(b);
+  const float e = fmaf(-b, y, 1.0f);
+  y = fmaf(e, y, y);
+  float q = a * y;
+  float r = fmaf(-b, q, a);
+  q = fmaf(r, y, q);
+  r = fmaf(-b, q, a);
+  return fmaf(r, y, q);
+}
+
 // ---------------------------------------------------------------- selection
 
 struct Selector {
@@ -311,7 +329,7 @@ __device__ __forceinline__ void eval_cfg(const KArch &A, const Tables &tb, const
       num = hide;
       den = x;
     }
-    const float F = (float)num / (float)den;
+    const float F = div_grid((float)num, (float)den);
     sc = (B > 0) ? Ed * F : __builtin_huge_valf();
   }
 }
@@ -366,7 +384,7 @@ __device__ __forceinline__ Terms eval_terms(const KArch &A, const Tables &tb, co
     num = hide;
     den = x;
   }
-  const float F = (float)num / (float)den;
+  const float F = div_grid((float)num, (float)den);
   t.Ed = B > 0 ? Ed : __builtin_huge_valf();
   t.F = B > 0 ? F : 0.0f;
   t.sc = B > 0 ? Ed * F : __builtin_huge_valf();

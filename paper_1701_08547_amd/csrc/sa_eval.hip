@@ -496,9 +496,12 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
         if (lane < k) wgk[w][lane] = mine;
       }
     }
-    if constexpr (TOPK) {
+    // only a split item's waves meet (kind is uniform over the workgroup, so
+    // every wave takes the same barriers); a packing item's waves go on to
+    // their next item without waiting for each other
+    if (TOPK && it.kind == 1) {
       __syncthreads();
-      if (it.kind == 1 && w == 0) {
+      if (w == 0) {
         const int64_t v = it.v < L.n_var ? (it.v > 0 ? it.v : 0) : L.n_var - 1;
         const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
         sel.count = 0;

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void sa_mlp_fwd_kernel(MlpDev M, co
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const float d = mlp_rows<false>(s, X[w], lane, u32x4_t{0u, 0u, 0u, 0u});
+    const float d = mlp_rows<false, 2>(s, X[w], lane, u32x4_t{0u, 0u, 0u, 0u});
     if (in) delta[row] = d;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();

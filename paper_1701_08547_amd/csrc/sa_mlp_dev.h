@@ -257,110 +257,119 @@ __device__ __forceinline__ f32x4_t mfma32(u32x4_t a, u32x4_t b, f32x4_t c) {
                                                  0, 0, 0);
 }
 
-// Eight values of an MFMA output pair (two row tiles) through GELU, packed
-// to bfloat16 in pairs: out[i][0..1] for row tile i.
-__device__ __forceinline__ void gelu_pack(const f32x4_t (&d)[2], const f32x2_t *tab, uint32_t (&out)[2][2]) {
-  float v[8];
+// The values of RT row tiles of an MFMA output through GELU, packed to
+// bfloat16 in pairs: out[i][0..1] for row tile i.  Eight values at a time,
+// so that eight table reads are in flight before the first multiply-add.
+template <int RT>
+__device__ __forceinline__ void gelu_pack(const f32x4_t (&d)[RT], const f32x2_t *tab, uint32_t (&out)[RT][2]) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i0 = 0; i0 < RT; i0 += 2) {
+    float v[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[4 * i + j] = d[i][j];
-  gelu_t_n<8>(v, tab);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    out[i][0] = pack_bf16(v[4 * i], v[4 * i + 1]);
-    out[i][1] = pack_bf16(v[4 * i + 2], v[4 * i + 3]);
+      for (int j = 0; j < 4; ++j) v[4 * i + j] = d[i0 + i][j];
+    gelu_t_n<8>(v, tab);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      out[i0 + i][0] = pack_bf16(v[4 * i], v[4 * i + 1]);
+      out[i0 + i][1] = pack_bf16(v[4 * i + 2], v[4 * i + 3]);
+    }
   }
 }
 
 // Delta of row `lane` of the wave's 64-row input block X (put_x rows; the
 // caller orders the writes before this call).  h1 = bf16(GELU(W1 x + b1)),
 // h2 = bf16(GELU(W2 h1 + b2)), Delta = w3 . h2 + b3, all three layers on the
-// matrix cores with fp32 accumulation, in two passes of 32 rows (row tiles
-// 2 p and 2 p + 1) so that one pass's first hidden layer fits in 32
-// registers.  A layer's output tiles (hidden units 16 t + 4 q + j of row r
-// at lane 16 q + r) are, packed in pairs, the B operands of the next layer
-// once its weight columns are permuted as in w2_column.  Input slice q = 3
-// (features 24..31) is zero.  The third layer multiplies every A row by w3,
-// so row 4 q of its result, which lane 16 q + r holds, is the sum for row r
-// of the row tile.  SHARED: slice 0 of every row is `xv` (put_x_cfg rows),
-// not read from X.
-template <bool SHARED>
+// matrix cores with fp32 accumulation, in 4 / RT passes of RT row tiles (16
+// rows each): every weight tile read from LDS serves the RT row tiles of a
+// pass, so more row tiles per pass read fewer weight bytes per row, and one
+// pass's first hidden layer takes 16 RT registers.  A layer's output tiles
+// (hidden units 16 t + 4 q + j of row r at lane 16 q + r) are, packed in
+// pairs, the B operands of the next layer once its weight columns are
+// permuted as in w2_column.  Input slice q = 3 (features 24..31) is zero.
+// The third layer multiplies every A row by w3, so row 4 q of its result,
+// which lane 16 q + r holds, is the sum for row r of the row tile.  SHARED:
+// slice 0 of every row is `xv` (put_x_cfg rows), not read from X.
+template <bool SHARED, int RT>
 __device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, int lane, u32x4_t xv) {
+  static_assert(RT == 2 || RT == 4, "row tiles per pass");
   const int r = lane & 15, q = lane >> 4;
   const int qx = q == 0 ? (SHARED ? 1 : 0) : (q < 3 ? q : 2);
   float delta = 0.0f;
 #pragma unroll 1
-  for (int p = 0; p < 2; ++p) {
-    u32x4_t xb[2];
+  for (int p = 0; p < 4 / RT; ++p) {
+    u32x4_t xb[RT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const u32x4_t x = *(const u32x4_t *)(X + (16 * (2 * p + i) + r) * kLdXin + 8 * qx);
+    for (int i = 0; i < RT; ++i) {
+      const u32x4_t x = *(const u32x4_t *)(X + (16 * (RT * p + i) + r) * kLdXin + 8 * qx);
       xb[i] = q == 3 ? u32x4_t{0u, 0u, 0u, 0u} : ((SHARED && q == 0) ? xv : x);
     }
-    // layer 1: hidden tile t -> two row tiles x 4 packed bf16 (two dwords).
+    // layer 1: hidden tile t -> RT row tiles x 4 packed bf16 (two dwords).
     // Software-pipelined: tile t + 1's MFMAs are issued before tile t's GELU,
     // so that the matrix cores work while the vector unit does the table GELU.
-    uint32_t h1[8][2][2];
-    auto l1 = [&](int t, f32x4_t (&d)[2]) {
+    uint32_t h1[8][RT][2];
+    auto l1 = [&](int t, f32x4_t (&d)[RT]) {
       const u32x4_t a = *(const u32x4_t *)(s.W1 + (16 * t + r) * kLdW1 + 8 * q);
       const f32x4_t bias = *(const f32x4_t *)(s.b1 + 16 * t + 4 * q);
-      d[0] = mfma32(a, xb[0], bias);
-      d[1] = mfma32(a, xb[1], bias);
+#pragma unroll
+      for (int i = 0; i < RT; ++i) d[i] = mfma32(a, xb[i], bias);
     };
-    f32x4_t d_cur[2], d_nxt[2];
+    f32x4_t d_cur[RT], d_nxt[RT];
     l1(0, d_cur);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       if (t < 7) l1(t + 1, d_nxt);
-      gelu_pack(d_cur, s.gelu, h1[t]);
+      gelu_pack<RT>(d_cur, s.gelu, h1[t]);
       if (t < 7) {
-        d_cur[0] = d_nxt[0];
-        d_cur[1] = d_nxt[1];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) d_cur[i] = d_nxt[i];
       }
       __builtin_amdgcn_sched_barrier(0);
     }
     // layers 2 and 3, pipelined the same way over the 8 output tiles; each
     // pair of tiles (a 32-unit chunk) feeds the third layer at once
-    auto l2 = [&](int ot, f32x4_t (&acc)[2]) {
+    auto l2 = [&](int ot, f32x4_t (&acc)[RT]) {
       const f32x4_t bias = *(const f32x4_t *)(s.b2 + 16 * ot + 4 * q);
-      acc[0] = bias;
-      acc[1] = bias;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) acc[i] = bias;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const u32x4_t a = *(const u32x4_t *)(s.W2 + (16 * ot + r) * kLdW2 + 32 * c + 8 * q);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < RT; ++i) {
           const u32x4_t b = {h1[2 * c][i][0], h1[2 * c][i][1], h1[2 * c + 1][i][0], h1[2 * c + 1][i][1]};
           acc[i] = mfma32(a, b, acc[i]);
         }
       }
     };
-    f32x4_t acc3[2] = {f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}, f32x4_t{0.0f, 0.0f, 0.0f, 0.0f}};
-    f32x4_t a_cur[2], a_nxt[2];
-    uint32_t h2[2][2][2];
+    f32x4_t acc3[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) acc3[i] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4_t a_cur[RT], a_nxt[RT];
+    uint32_t h2[2][RT][2];
     l2(0, a_cur);
 #pragma unroll
     for (int ot = 0; ot < 8; ++ot) {
       if (ot < 7) l2(ot + 1, a_nxt);
-      gelu_pack(a_cur, s.gelu, h2[ot & 1]);
+      gelu_pack<RT>(a_cur, s.gelu, h2[ot & 1]);
       if (ot & 1) {
         const u32x4_t a3 = *(const u32x4_t *)(s.w3p + 32 * (ot >> 1) + 8 * q);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < RT; ++i) {
           const u32x4_t b = {h2[0][i][0], h2[0][i][1], h2[1][i][0], h2[1][i][1]};
           acc3[i] = mfma32(a3, b, acc3[i]);
         }
       }
       if (ot < 7) {
-        a_cur[0] = a_nxt[0];
-        a_cur[1] = a_nxt[1];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) a_cur[i] = a_nxt[i];
       }
       __builtin_amdgcn_sched_barrier(0);
     }
     // lane l = 16 q + r owns row l, which is row r of row tile q
-    delta = q == 2 * p ? acc3[0][0] : delta;
-    delta = q == 2 * p + 1 ? acc3[1][0] : delta;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) delta = q == RT * p + i ? acc3[i][0] : delta;
   }
   return delta + s.b3;
 }
