@@ -427,10 +427,17 @@ __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
 
 // ---------------------------------------------------------------- planned batches
 
-// Persistent kernel over a plan's workgroup items (static stride over the
-// grid).  kind 0 items: each wave evaluates whole segments and writes their
-// rows.  kind 1 items: each wave selects over its part of one segment, the
-// parts meet in LDS and wave 0 writes the row (or the item's fragment).
+// Persistent kernel over a plan's workgroup items (the plan lists them
+// longest first).  Workgroup j takes item j; with more items than workgroups
+// the rest are taken from the plan's queue, one ticket per item, the next
+// ticket fetched while the current item is evaluated, so that the workgroups
+// finish close together whatever the item sizes.  A launch takes exactly
+// n_items tickets (n_items - G items, then one empty ticket per workgroup),
+// and the workgroup holding the last one returns the counter to zero for the
+// next launch (stream-ordered launches of one plan, replayed graphs
+// included).  kind 0 items: each wave evaluates whole segments and writes
+// their rows.  kind 1 items: each wave selects over its part of one segment,
+// the parts meet in LDS and wave 0 writes the row (or the item's fragment).
 template <Mode MODE, bool HAS_GRID, bool TOPK, int ITEMS, int WPB>
 __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev P) {
   extern __shared__ __align__(16) uint8_t dyn_lds[];
@@ -439,6 +446,7 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
   __shared__ uint8_t tab_blim[kMaxWB + 2];
   __shared__ WaveLds wl[WPB];
   __shared__ uint64_t wgk[WPB][SA_K_MAX];
+  __shared__ uint32_t s_ticket;
 
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -453,7 +461,20 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
   sel.count = 0;
   sel.theta = kThetaInit;
 
-  for (int64_t item = blockIdx.x; item < P.n_items; item += gridDim.x) {
+  const uint32_t n_items = (uint32_t)P.n_items, n_wg = gridDim.x;
+  const bool queued = n_items > n_wg;
+  uint32_t ticket = blockIdx.x;
+  while (ticket < n_items) {
+    const int64_t item = ticket;
+    uint32_t next = n_items;
+    if (queued) {
+      __syncthreads();  // every wave has read s_ticket
+      if (tid == 0) {
+        const uint32_t t = atomicAdd(&P.queue[0], 1u);
+        if (t == n_items - 1u) atomicExch(&P.queue[0], 0u);  // the launch's last ticket
+        next = n_wg + t;
+      }
+    }
     const PlanItem it = P.items[item];
     const PlanWave pw = P.waves[item * WPB + w];
     if (it.kind == 0) {
@@ -523,6 +544,10 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
       }
       __syncthreads();
     }
+    if (!queued) break;
+    if (tid == 0) s_ticket = next;
+    __syncthreads();
+    ticket = s_ticket;
   }
 }
 

@@ -126,6 +126,9 @@ struct PlanDev {
   const PlanWave *waves;   // n_items x wpb
   const PlanSplit *splits;
   int64_t n_items, n_splits;
+  // the item queue's ticket counter (zero between launches: the workgroup
+  // taking a launch's last ticket returns it to zero)
+  uint32_t *queue;
 };
 
 // Launch shape of a plan: evaluations per wave part, items per lane (1, 2,

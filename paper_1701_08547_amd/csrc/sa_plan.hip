@@ -96,9 +96,42 @@ void decompose(const int64_t *seg, int64_t n_var, const sa::PlanShape &S, std::v
   }
 }
 
-// Byte offsets of the three arrays inside the device table.
+// Items in descending order of their longest wave part (evaluations plus the
+// per-segment charge), the order the kernel's workgroups take them from its
+// queue: the long items start first and the last ones taken are short, so
+// the workgroups finish close together (greedy list scheduling of the
+// longest first).  Slots and splits name items by slot, not by position, so
+// the order is free.
+void order_items(const int64_t *seg, const sa::PlanShape &S, std::vector<sa::PlanItem> &items,
+                 std::vector<sa::PlanWave> &waves) {
+  const int64_t kSegCharge = 256, wpb = S.wpb, n = (int64_t)items.size();
+  std::vector<int64_t> cost(n), order(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c = 0;
+    for (int64_t w = 0; w < wpb; ++w) {
+      const sa::PlanWave &pw = waves[i * wpb + w];
+      const int64_t cw = items[i].kind == 0 ? seg[pw.v1] - seg[pw.v0] + kSegCharge * (pw.v1 - pw.v0)
+                                            : pw.e1 - pw.e0 + kSegCharge;
+      c = std::max(c, cw);
+    }
+    cost[i] = c;
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+  std::vector<sa::PlanItem> it(n);
+  std::vector<sa::PlanWave> wv(waves.size());
+  for (int64_t j = 0; j < n; ++j) {
+    it[j] = items[order[j]];
+    for (int64_t w = 0; w < wpb; ++w) wv[j * wpb + w] = waves[order[j] * wpb + w];
+  }
+  items.swap(it);
+  waves.swap(wv);
+}
+
+// Byte offsets of the three arrays and the item queue inside the device
+// table.
 struct TableLayout {
-  size_t items, waves, splits, total;
+  size_t items, waves, splits, queue, total;
 };
 
 TableLayout table_layout(const sa_plan *p) {
@@ -108,8 +141,8 @@ TableLayout table_layout(const sa_plan *p) {
   t.items = 0;
   t.waves = (bi + 255) / 256 * 256;
   t.splits = t.waves + (bw + 255) / 256 * 256;
-  t.total = t.splits + (bs + 255) / 256 * 256;
-  if (t.total == 0) t.total = 256;
+  t.queue = t.splits + (bs + 255) / 256 * 256;
+  t.total = t.queue + 256;
   return t;
 }
 
@@ -158,6 +191,7 @@ sa_status sa_plan_layout(const int64_t *seg_host, int64_t n_variants, int64_t n_
   std::vector<sa::PlanSplit> sp;
   int64_t slots = 0;
   decompose(seg_host, n_variants, S, it, wv, sp, slots);
+  order_items(seg_host, S, it, wv);
   if (n_items) *n_items = (int64_t)it.size();
   if (n_splits) *n_splits = (int64_t)sp.size();
   if (n_slots) *n_slots = slots;
@@ -202,6 +236,11 @@ sa_status sa_plan_create(const int64_t *seg_host, int64_t n_variants, int64_t n_
                 S.items, S.wpb);
   sa_plan *p = new sa_plan();
   decompose(seg_host, n_variants, S, p->items, p->waves, p->splits, p->n_slots);
+  order_items(seg_host, S, p->items, p->waves);
+  if ((int64_t)p->items.size() > (int64_t)INT32_MAX) {
+    delete p;
+    return fail(SA_ERR_UNSUPPORTED, "more than 2^31 workgroup items");
+  }
   p->n_var = n_variants;
   p->n_evals = n_evals;
   p->k = k;
@@ -233,12 +272,16 @@ sa_status sa_plan_bind(sa_plan *plan, void *table, size_t table_bytes, void *str
       (bw && (e = hipMemcpyAsync(base + t.waves, plan->waves.data(), bw, hipMemcpyHostToDevice, s)) != hipSuccess) ||
       (bs && (e = hipMemcpyAsync(base + t.splits, plan->splits.data(), bs, hipMemcpyHostToDevice, s)) != hipSuccess))
     return hip_fail(e, "hipMemcpyAsync (plan table)");
+  static const uint32_t kQueueZero[1] = {0u};
+  if ((e = hipMemcpyAsync(base + t.queue, kQueueZero, sizeof(kQueueZero), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "hipMemcpyAsync (plan queue)");
   plan->n_cu = n_cu > 0 ? n_cu : 1;
   plan->pd.items = (const sa::PlanItem *)(base + t.items);
   plan->pd.waves = (const sa::PlanWave *)(base + t.waves);
   plan->pd.splits = (const sa::PlanSplit *)(base + t.splits);
   plan->pd.n_items = plan->n_items;
   plan->pd.n_splits = plan->n_splits;
+  plan->pd.queue = (uint32_t *)(base + t.queue);
   return SA_OK;
 }
 

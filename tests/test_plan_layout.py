@@ -44,9 +44,11 @@ def _check(seg, shape):
         size = seg[v + 1] - seg[v]
         if v in parts:
             assert packed_of[v] == -1 and size > tile
-            # wave parts tile the segment exactly, in order
+            # wave parts tile the segment exactly, in slot order (items are
+            # listed longest first, so a split segment's items need not be
+            # adjacent)
             edges = []
-            for i, _ in parts[v]:
+            for i, _ in sorted(parts[v], key=lambda x: x[1]):
                 for w in range(wpb):
                     edges.append((waves[i, w, 0], waves[i, w, 1]))
             assert edges[0][0] == seg[v] and edges[-1][1] == seg[v + 1]
@@ -63,9 +65,19 @@ def _check(seg, shape):
             assert slots == [-1] and v not in split_v
         else:
             first, n = split_v[v]
-            assert n == len(its) and slots == list(range(first, first + n))
+            assert n == len(its) and sorted(slots) == list(range(first, first + n))
             used.update(slots)
     assert len(used) == L["n_slots"] and (not used or max(used) == L["n_slots"] - 1)
+    # the queue order: items by non-increasing longest wave part
+    # (evaluations plus 256 per segment)
+    cost = []
+    for i, (kind, slot, v) in enumerate(items):
+        c = 0
+        for w in range(wpb):
+            e0, e1, v0, v1 = waves[i, w]
+            c = max(c, (seg[v1] - seg[v0] + 256 * (v1 - v0)) if kind == 0 else (e1 - e0 + 256))
+        cost.append(c)
+    assert all(a >= b for a, b in zip(cost, cost[1:]))
 
 
 SHAPES = [(256, 4, 4), (1024, 1, 8), (4096, 4, 4), (8192, 2, 16)]
@@ -118,8 +130,10 @@ def test_plan_is_a_host_object_bound_to_a_caller_table():
     assert L.sa_plan_create(seg.ctypes.data_as(api.ctypes.c_void_p), 4, 70100, 8, None, api.ctypes.byref(h)) == 0
     lay = api.plan_layout(seg)
     nbytes = L.sa_plan_device_bytes(h)
+    # items, waves and splits, each rounded to 256 bytes, then 256 bytes of
+    # item queue
     want = sum((b + 255) // 256 * 256 for b in (len(lay["items"]) * 16, lay["waves"].shape[0] * 4 * 32,
-                                                  len(lay["splits"]) * 32))
+                                                  len(lay["splits"]) * 32)) + 256
     assert nbytes == want and nbytes % 256 == 0
     assert L.sa_plan_device_bytes(None) == 0
     assert L.sa_plan_bind(h, None, nbytes, None) == -1                                    # NULL table
