@@ -125,6 +125,59 @@ def test_plan_graph_capture_replays():
             assert torch.equal(eager[key].view(torch.int32), outs[key].view(torch.int32)), (r, key)
 
 
+def test_plan_item_queue_across_launches_and_replays():
+    """A plan with far more workgroup items than resident workgroups takes
+    its items from the ticket queue in its table.  The queue must be back at
+    zero after every launch whatever kernel took it: the scoring pass, the
+    top-k pass over keys (another kernel, another grid) and replays of a
+    captured graph, interleaved, each equal to the oracle."""
+    g = np.random.default_rng(5)
+    sizes = g.integers(1, 400, 40000)
+    sizes[::97] = g.integers(2000, 9000, sizes[::97].size)  # some segments cut into several items
+    b = workloads.custom_batch(91, sizes, with_grid=True, name="plan-queue")
+    a = oracle.arch_cdna4()
+    var, cfg = api.device_batch(b)
+    plan = api.Plan(b.seg, k=8, shape=(256, 1, 4))
+    say("queue plan items", plan.n_items, "splits", plan.n_splits, "evaluations", b.n_evals)
+    assert plan.n_items > 8 * 256  # more than any grid of this shape resides
+    ref = oracle.run(a, b.variants, b.configs(), k=8, want_occ=True, want_f32=True, want_f64=False)
+    ws = api.Workspace(plan.workspace_bytes, "cuda")
+    outs = {"occ": torch.empty(b.n_evals, dtype=torch.int32, device="cuda"),
+            "score": torch.empty(b.n_evals, dtype=torch.float32, device="cuda"),
+            "idx": torch.empty((b.n_var, 8), dtype=torch.int32, device="cuda"),
+            "val": torch.empty((b.n_var, 8), dtype=torch.float32, device="cuda")}
+
+    def host(o):
+        return {key: t.cpu().numpy() for key, t in o.items()}
+
+    for r in range(2):
+        plan.score(a, var, cfg, outputs=outs, workspace=ws)
+        torch.cuda.synchronize()
+        check(ref, host(outs))
+        idx, val = plan.topk(outs["score"], cfg["seg"], workspace=ws)
+        torch.cuda.synchronize()
+        check({"idx": ref["idx"], "val": ref["val"]}, {"idx": idx.cpu().numpy(), "val": val.cpu().numpy()})
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.score(a, var, cfg, outputs=outs, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.score(a, var, cfg, outputs=outs, workspace=ws)
+    for r in range(3):
+        for t in outs.values():
+            t.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        check(ref, host(outs))
+        idx, val = plan.topk(outs["score"], cfg["seg"], workspace=ws)  # eager, between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(idx.cpu().numpy(), ref["idx"])
+
+
 def test_autotuner_picks_a_valid_shape():
     b = workloads.custom_batch(81, [5000, 64, 300000, 7, 20000, 0], with_grid=True, name="plan-tune")
     a = oracle.arch_cdna4()
