@@ -171,7 +171,7 @@ constexpr int kMaxPartials = 256;             // workgroups (gradient partials) 
 constexpr int kLdR = kTrainRows + 8;          // row stride of the per-pass blocks (bf16), padded
 
 struct __align__(16) TrainLds {
-  MlpLdsT f;                        // forward: the inference staging (x64 weights, GELU pieces)
+  MlpLdsT f;                        // forward: the inference staging (scaled weights, GELU pieces)
   uint16_t W2b[kMH * kLdW2];        // backward: W2b[k][p] = W2[w2_column(p)][k]
   float w3[kMH];                    // w3 as the forward uses it (its bf16 value)
   uint16_t gA2t[kMH * kLdR];        // dL/da2 [hidden][row of the pass], bf16
@@ -182,7 +182,7 @@ struct __align__(16) TrainLds {
   float tail[kTrainWaves][2];       // per-wave b3 gradient and loss
 };
 
-// a of a scaled pre-activation t = 64 a + 512.
+// a of a scaled pre-activation u = a / 16 + 1/2.
 __device__ __forceinline__ float unscale(float t) { return (t - kTOrigin) * (1.0f / kTScale); }
 
 // LOSS 0: squared error against target (dL/dDelta = 2 (Delta - r) / n).

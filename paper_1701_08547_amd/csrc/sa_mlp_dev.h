@@ -72,20 +72,26 @@ __device__ __forceinline__ float gelu_grad(float a) {
 }
 
 // Inference GELU from an LDS table of linear pieces.  The forward pass works
-// on the scaled pre-activation t = 64 a + 512: the weights of the first two
-// layers are staged multiplied by 64 (exact in bfloat16) and their biases as
-// 64 b + 512, so the matrix cores deliver t directly.  On [i, i + 1) the
-// table holds the chord of GELU between a_i = (i - 512) / 64 and a_i+1 as
-// GELU ~ g0_i + t g1_i, so one multiply-add gives the value: the chord's
-// error is at most h^2 / 8 max|GELU''| = 2.4e-5 (h = 1/64, GELU'' = phi(a)
-// (2 - a^2) peaks at 2 phi(0)), well below the bfloat16 rounding that
-// follows.  Piece 0 (a < -8 + 1/64) is zero and piece 1023 (a >= 8 - 1/64) is
-// the identity a = (t - 512) / 64; an index clamped to [0, 1023] then also
-// covers every t outside [0, 1024): GELU(a) differs from 0 below a = -8 and
-// from a above a = 8 by less than 1e-14.
+// on the scaled pre-activation u = a / 16 + 1/2: the weights of the first two
+// layers are staged multiplied by 1/16 (exact in bfloat16) and their biases
+// as b / 16 + 1/2, so the matrix cores deliver u directly, and u in [0, 1)
+// covers a in [-8, 8).  Piece i covers u in [i, i + 1) / 1024 (a width of
+// 1/64 in a) and holds the chord of GELU between a_i = (i - 512) / 64 and
+// a_i+1 as GELU ~ g0_i + u g1_i, so one multiply-add gives the value: the
+// chord's error is at most h^2 / 8 max|GELU''| = 2.4e-5 (h = 1/64, GELU'' =
+// phi(a) (2 - a^2) peaks at 2 phi(0)), well below the bfloat16 rounding that
+// follows.  Piece 0 (a < -8 + 1/64) is zero and piece 1023 (a >= 8 - 1/64)
+// is the identity a = 16 (u - 1/2); so an index clamped to [0, 1023] also
+// covers every u outside [0, 1): GELU(a) differs from 0 below a = -8 and
+// from a above a = 8 by less than 1e-14.  The index of two values comes from
+// one conversion: v_cvt_pknorm_u16_f32 clamps both to [0, 1] and rounds
+// them to 16-bit fractions m = round(65535 u), whose top ten bits are the
+// piece (m / 64 differs from 1024 u by less than 1/64 + 1/128 of a piece, so
+// near a piece's edge the neighbouring chord may be taken: both pass through
+// the edge, and the chord extended by that much stays within 1e-7 of GELU).
 constexpr int kGeluN = 1024;
-constexpr float kTScale = 64.0f;
-constexpr float kTOrigin = 512.0f;
+constexpr float kTScale = 1.0f / 16.0f;
+constexpr float kTOrigin = 0.5f;
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double gelu_exact(double a) { return 0.5 * a * erfc(-a * 0.70710678118654752440); }
@@ -96,21 +102,29 @@ __device__ __forceinline__ f32x2_t gelu_piece(int i) {
   if (i >= kGeluN - 1) return f32x2_t{-kTOrigin / kTScale, 1.0f / kTScale};
   const double a0 = (double)(i - 512) / 64.0, a1 = (double)(i + 1 - 512) / 64.0;
   const double y0 = gelu_exact(a0), y1 = gelu_exact(a1);
-  const double g1 = y1 - y0;
-  return f32x2_t{(float)(y0 - (double)i * g1), (float)g1};
+  const double g1 = (y1 - y0) * kGeluN;  // per unit of u
+  return f32x2_t{(float)(y0 - (double)i / kGeluN * g1), (float)g1};
 }
 
-// GELU of N scaled pre-activations in place.  All table positions are
-// computed and all reads issued before the first multiply-add, so that the
-// reads' latency overlaps.
+// GELU of N (even) scaled pre-activations in place.  All table positions
+// are computed and all reads issued before the first multiply-add, so that
+// the reads' latency overlaps.
 template <int N>
 __device__ __forceinline__ void gelu_t_n(float (&t)[N], const f32x2_t *tab) {
+  static_assert(N % 2 == 0, "pairs of values");
+  const char *base = (const char *)tab;
   f32x2_t c[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) c[i] = tab[(uint32_t)__builtin_amdgcn_fmed3f(t[i], 0.0f, (float)(kGeluN - 1))];
+  for (int i = 0; i < N; i += 2) {
+    const uint32_t m = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pknorm_u16(t[i], t[i + 1]));
+    // byte offsets 8 (m / 64) of the two 16-bit fractions
+    c[i] = *(const f32x2_t *)(base + ((m >> 3) & 0x1FF8u));
+    c[i + 1] = *(const f32x2_t *)(base + ((m >> 19) & 0x1FF8u));
+  }
 #pragma unroll
   for (int i = 0; i < N; ++i) t[i] = fmaf(t[i], c[i].y, c[i].x);
 }
+
 
 // ---------------------------------------------------------------- features
 
@@ -171,10 +185,10 @@ __device__ __forceinline__ void config_features(float *f, int32_t T, int32_t U, 
 constexpr int kLdXin = kMF;  // input row stride (bf16): the 24 features, no padding
 
 struct __align__(16) MlpLdsT {
-  uint16_t W1[kMH * kLdW1];  // 64 W1[h][k]
-  uint16_t W2[kMH * kLdW2];  // 64 W2[o][.], columns permuted per 32-wide chunk (see w2_column)
+  uint16_t W1[kMH * kLdW1];  // W1[h][k] / 16
+  uint16_t W2[kMH * kLdW2];  // W2[o][.] / 16, columns permuted per 32-wide chunk (see w2_column)
   uint16_t w3p[kMH];         // w3 in the same permuted order
-  float b1[kMH], b2[kMH];    // 64 b + 512
+  float b1[kMH], b2[kMH];    // b / 16 + 1/2
   f32x2_t gelu[kGeluN];      // pieces (g0, g1)
   float mean[kMF], inv_std[kMF];
   float b3;
@@ -194,17 +208,18 @@ __device__ __forceinline__ int w2_position(int u) {
   return m < 16 ? 32 * c + 8 * (m >> 2) + (m & 3) : 32 * c + 8 * ((m - 16) >> 2) + 4 + (m & 3);
 }
 
-// bfloat16 bits times 64 (exact: only the exponent changes; zero stays zero).
-__device__ __forceinline__ uint16_t bf16_x64(uint16_t b) {
+// bfloat16 bits times kTScale (exact: only the exponent changes; zero stays
+// zero; weights this small never reach the subnormals).
+__device__ __forceinline__ uint16_t bf16_scaled(uint16_t b) {
   const float x = __builtin_bit_cast(float, (uint32_t)b << 16) * kTScale;
   return (uint16_t)(__builtin_bit_cast(uint32_t, x) >> 16);
 }
 
 __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthreads) {
-  for (int i = tid; i < kMH * kMK; i += nthreads) s.W1[(i / kMK) * kLdW1 + (i % kMK)] = bf16_x64(M.W1[i]);
+  for (int i = tid; i < kMH * kMK; i += nthreads) s.W1[(i / kMK) * kLdW1 + (i % kMK)] = bf16_scaled(M.W1[i]);
   for (int i = tid; i < kMH * kMH; i += nthreads) {
     const int o = i / kMH, p = i % kMH;
-    s.W2[o * kLdW2 + p] = bf16_x64(M.W2[o * kMH + w2_column(p)]);
+    s.W2[o * kLdW2 + p] = bf16_scaled(M.W2[o * kMH + w2_column(p)]);
   }
   for (int i = tid; i < kMH; i += nthreads) {
     s.b1[i] = fmaf(M.b1[i], kTScale, kTOrigin);
