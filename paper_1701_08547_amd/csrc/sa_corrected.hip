@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64 * kCorrWaves) void sa_corrected_kernel(EvalLaunc
         if (L.occ && in) L.occ[row] = t.W;
         const bool legal = t.B > 0;
         config_features(f, T, U, R, G, HAS_GRID, A.n_cu, t.WB, t.gw, t.gr, t.gs, t.B, t.W, t.Ed, t.F, t.sc);
-        put_x_cfg(s, Xw, lane, f, !legal);
+        put_x_cfg(s, Xw, lane, f);
         wave_lds_sync();
         const float delta = mlp_rows<true, kCorrRT>(s, Xw, lane, xv);
         wave_lds_sync();

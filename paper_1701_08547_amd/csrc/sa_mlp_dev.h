@@ -235,7 +235,9 @@ __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthread
 }
 
 // Features i0 .. i0 + 2 n - 1 as network inputs: bf16((f - mean) * inv_std),
-// packed in pairs.
+// packed in pairs.  (One multiply-add with a precomputed -mean inv_std
+// would lose the exact difference f - mean: near-constant features, whose
+// inv_std is large, then come out visibly wrong.)
 template <int N>
 __device__ __forceinline__ void pack_inputs(const MlpLdsT &s, const float *f, int i0, uint32_t *p) {
 #pragma unroll
@@ -258,13 +260,15 @@ __device__ __forceinline__ void put_x(const MlpLdsT &s, uint16_t *X, int row, co
 
 // The same row when inputs 0..7 (slice 0) are the variant's and shared by
 // every row of the block: only slices 1 and 2 (inputs 8..23) are written.
-__device__ __forceinline__ void put_x_cfg(const MlpLdsT &s, uint16_t *X, int row, const float *f, bool zero) {
+// Rows of illegal configurations keep their non-finite inputs: every
+// column of a contraction is one row, so they reach only their own Delta,
+// which the caller discards.
+__device__ __forceinline__ void put_x_cfg(const MlpLdsT &s, uint16_t *X, int row, const float *f) {
   uint32_t p[8];
   pack_inputs<8>(s, f, 8, p);
   u32x4_t *dst = (u32x4_t *)(X + row * kLdXin);
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
-    dst[j + 1] = zero ? u32x4_t{0u, 0u, 0u, 0u} : u32x4_t{p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]};
+  for (int j = 0; j < 2; ++j) dst[j + 1] = u32x4_t{p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]};
 }
 
 __device__ __forceinline__ f32x4_t mfma32(u32x4_t a, u32x4_t b, f32x4_t c) {
