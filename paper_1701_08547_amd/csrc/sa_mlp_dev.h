@@ -116,10 +116,15 @@ __device__ __forceinline__ void gelu_t_n(float (&t)[N], const f32x2_t *tab) {
   f32x2_t c[N];
 #pragma unroll
   for (int i = 0; i < N; i += 2) {
-    const uint32_t m = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pknorm_u16(t[i], t[i + 1]));
-    // byte offsets 8 (m / 64) of the two 16-bit fractions
-    c[i] = *(const f32x2_t *)(base + ((m >> 3) & 0x1FF8u));
-    c[i + 1] = *(const f32x2_t *)(base + ((m >> 19) & 0x1FF8u));
+    uint32_t m = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pknorm_u16(t[i], t[i + 1]));
+    // Both 16-bit fractions cut to their piece (the top ten bits) at once;
+    // the byte offsets 8 piece are then one field extract (low half) and one
+    // shift (high half).  The empty statement keeps the compiler from folding
+    // the mask into each offset, which takes two instructions apiece.
+    m &= 0xFFC0FFC0u;
+    __asm__ volatile("" : "+v"(m));
+    c[i] = *(const f32x2_t *)(base + __builtin_amdgcn_ubfe(m, 3u, 13u));
+    c[i + 1] = *(const f32x2_t *)(base + (m >> 19));
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) t[i] = fmaf(t[i], c[i].y, c[i].x);
