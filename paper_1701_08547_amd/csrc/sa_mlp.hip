@@ -240,14 +240,17 @@ __global__ __launch_bounds__(kTrainThreads) void sa_train_kernel(MlpDev M, const
       s.Xt[(8 * q + 2 * i) * kLdR + col] = (uint16_t)(xb[i] & 0xFFFFu);
       s.Xt[(8 * q + 2 * i + 1) * kLdR + col] = (uint16_t)(xb[i] >> 16);
     }
+    // the contraction's operand carries the folded first-layer bias in
+    // inputs 24..26, as inference's does (the weight gradient above sees the
+    // network's zeros there)
+    if (q == 3) xb = u32x4_t{kOnes24, kOnes26, 0u, 0u};
     // layer 1 (scaled pre-activations kept for the backward pass)
     f32x4_t t1[8];
     uint32_t h1[8][2];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const u32x4_t a = *(const u32x4_t *)(s.f.W1 + (16 * t + r) * kLdW1 + 8 * q);
-      const f32x4_t bias = *(const f32x4_t *)(s.f.b1 + 16 * t + 4 * q);
-      t1[t] = mfma32(a, xb, bias);
+      t1[t] = mfma32(a, xb, f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
       float v[4] = {t1[t][0], t1[t][1], t1[t][2], t1[t][3]};
       gelu_t_n<4>(v, s.f.gelu);
       h1[t][0] = pack_bf16(v[0], v[1]);

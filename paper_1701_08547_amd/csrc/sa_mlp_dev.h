@@ -188,12 +188,15 @@ __device__ __forceinline__ void config_features(float *f, int32_t T, int32_t U, 
 // ---------------------------------------------------------------- forward pass
 
 constexpr int kLdXin = kMF;  // input row stride (bf16): the 24 features, no padding
+// MFMA operand slice of inputs 24..31: 1, 1 | 1, 0 | 0, 0 | 0, 0 (bfloat16
+// pairs, low half first), the ones that carry the folded first-layer bias
+constexpr uint32_t kOnes24 = 0x3F803F80u, kOnes26 = 0x00003F80u;
 
 struct __align__(16) MlpLdsT {
   uint16_t W1[kMH * kLdW1];  // W1[h][k] / 16
   uint16_t W2[kMH * kLdW2];  // W2[o][.] / 16, columns permuted per 32-wide chunk (see w2_column)
   uint16_t w3p[kMH];         // w3 in the same permuted order
-  float b1[kMH], b2[kMH];    // b / 16 + 1/2
+  float b2[kMH];             // b2 / 16 + 1/2 (b1 is folded into W1, see load_weights_t)
   f32x2_t gelu[kGeluN];      // pieces (g0, g1)
   float mean[kMF], inv_std[kMF];
   float b3;
@@ -220,14 +223,36 @@ __device__ __forceinline__ uint16_t bf16_scaled(uint16_t b) {
   return (uint16_t)(__builtin_bit_cast(uint32_t, x) >> 16);
 }
 
+// The first layer's bias enters its contraction: inputs 24..26 of every row
+// (padding, zero in the network) are 1 in the MFMA operand (kOnes24 / kOnes26,
+// the slice of inputs 24..31), and the staged W1 columns 24..26 hold the scaled
+// bias v = b1 / 16 + 1/2 split into three bfloat16 parts, hi + mid + lo = v
+// exactly (each part takes the next 8 significant bits of the remainder), so
+// the first layer reads no bias tile.  W1's own columns 24..31 multiply
+// zero inputs in the network and are not staged for 24..26.
+__device__ __forceinline__ uint16_t bf16_rn(float x) { return (uint16_t)(pack_bf16(x, 0.0f) & 0xFFFFu); }
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
 __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthreads) {
-  for (int i = tid; i < kMH * kMK; i += nthreads) s.W1[(i / kMK) * kLdW1 + (i % kMK)] = bf16_scaled(M.W1[i]);
+  for (int i = tid; i < kMH * kMK; i += nthreads) {
+    const int k = i % kMK;
+    if (k >= kMF && k < kMF + 3) continue;
+    s.W1[(i / kMK) * kLdW1 + k] = bf16_scaled(M.W1[i]);
+  }
+  for (int i = tid; i < kMH; i += nthreads) {
+    const float v = fmaf(M.b1[i], kTScale, kTOrigin);
+    const uint16_t hi = bf16_rn(v);
+    const float r1 = v - bf16_value(hi);
+    const uint16_t mid = bf16_rn(r1);
+    s.W1[i * kLdW1 + kMF] = hi;
+    s.W1[i * kLdW1 + kMF + 1] = mid;
+    s.W1[i * kLdW1 + kMF + 2] = bf16_rn(r1 - bf16_value(mid));
+  }
   for (int i = tid; i < kMH * kMH; i += nthreads) {
     const int o = i / kMH, p = i % kMH;
     s.W2[o * kLdW2 + p] = bf16_scaled(M.W2[o * kMH + w2_column(p)]);
   }
   for (int i = tid; i < kMH; i += nthreads) {
-    s.b1[i] = fmaf(M.b1[i], kTScale, kTOrigin);
     s.b2[i] = fmaf(M.b2[i], kTScale, kTOrigin);
     s.w3p[i] = M.w3[w2_column(i)];
   }
@@ -311,7 +336,8 @@ __device__ __forceinline__ void gelu_pack(const f32x4_t (&d)[RT], const f32x2_t 
 // pass's first hidden layer takes 16 RT registers.  A layer's output tiles
 // (hidden units 16 t + 4 q + j of row r at lane 16 q + r) are, packed in
 // pairs, the B operands of the next layer once its weight columns are
-// permuted as in w2_column.  Input slice q = 3 (features 24..31) is zero.
+// permuted as in w2_column.  Input slice q = 3 (inputs 24..31) is
+// kOnes24 / kOnes26: the first layer's bias is part of its contraction.
 // The third layer multiplies every A row by w3, so row 4 q of its result,
 // which lane 16 q + r holds, is the sum for row r of the row tile.  SHARED:
 // slice 0 of every row is `xv` (put_x_cfg rows), not read from X.
@@ -327,7 +353,7 @@ __device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, i
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       const u32x4_t x = *(const u32x4_t *)(X + (16 * (RT * p + i) + r) * kLdXin + 8 * qx);
-      xb[i] = q == 3 ? u32x4_t{0u, 0u, 0u, 0u} : ((SHARED && q == 0) ? xv : x);
+      xb[i] = q == 3 ? u32x4_t{kOnes24, kOnes26, 0u, 0u} : ((SHARED && q == 0) ? xv : x);
     }
     // layer 1: hidden tile t -> RT row tiles x 4 packed bf16 (two dwords).
     // Software-pipelined: tile t + 1's MFMAs are issued before tile t's GELU,
@@ -335,9 +361,8 @@ __device__ __forceinline__ float mlp_rows(const MlpLdsT &s, const uint16_t *X, i
     uint32_t h1[8][RT][2];
     auto l1 = [&](int t, f32x4_t (&d)[RT]) {
       const u32x4_t a = *(const u32x4_t *)(s.W1 + (16 * t + r) * kLdW1 + 8 * q);
-      const f32x4_t bias = *(const f32x4_t *)(s.b1 + 16 * t + 4 * q);
 #pragma unroll
-      for (int i = 0; i < RT; ++i) d[i] = mfma32(a, xb[i], bias);
+      for (int i = 0; i < RT; ++i) d[i] = mfma32(a, xb[i], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
     };
     f32x4_t d_cur[RT], d_nxt[RT];
     l1(0, d_cur);
