@@ -694,7 +694,7 @@ def corrected_leg(arch, var, cfg, n_var, n_evals, sur, steps: int) -> dict:
                          "frac": tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                          "note": "39,168 algorithmic FLOP per evaluation (24->128->128->1; the padding of the inputs "
                                  "to 32 is not counted); "
-                                 "bound by LDS reads first (the GELU table and the weight tiles, about 257 KiB per 64 evaluations), vector issue second; the matrix cores are about a third busy (SQ counters)"}}
+                                 "bound by LDS reads first (the GELU table and the weight tiles, about 245 KiB per 64 evaluations), vector issue second; the matrix cores are about a third busy (SQ counters)"}}
 
 
 if __name__ == "__main__":
