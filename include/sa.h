@@ -443,11 +443,16 @@ sa_status sa_plan_create(const int64_t *seg_host, int64_t n_variants, int64_t n_
                          const sa_plan_shape *shape /* NULL = 4096, 4, 4 */, sa_plan **out);
 /* Frees the host object only (never the bound table, which the caller owns). */
 sa_status sa_plan_destroy(sa_plan *plan);
-/* Bytes of the device table of a plan (0 for a NULL plan); a multiple of 256. */
+/* Bytes of the device table of a plan (0 for a NULL plan); a multiple of 256.
+ * The table holds the workgroup items (longest first), their wave parts, the
+ * split records and a 256-byte item queue: with more items than the launch
+ * has workgroups, the workgroups take the rest from a ticket counter there.
+ * Each launch leaves the counter at zero, so launches of one plan (replays
+ * of captured graphs included) must run in stream order, not concurrently. */
 size_t sa_plan_device_bytes(const sa_plan *plan);
 /* Copies the plan's decomposition into `table` (device memory, 256-byte
- * aligned, at least sa_plan_device_bytes(plan) bytes, caller-owned) with
- * hipMemcpyAsync on `stream`, and records `table` and the current device's
+ * aligned, at least sa_plan_device_bytes(plan) bytes, caller-owned) and
+ * zeroes its item queue, with hipMemcpyAsync on `stream`, and records `table` and the current device's
  * compute-unit count in the plan.  The copy reads the plan's host memory when
  * `stream` reaches it: keep the plan alive until then, and keep `table`
  * alive and unmodified while launches of the plan are pending.  Rebinding
