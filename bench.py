@@ -502,12 +502,13 @@ def c4_leg(arch, sur) -> dict:
             "seconds": time.perf_counter() - t0}
 
 
-def training_leg(epochs: int, n: int = 1 << 20, batch: int = 4096) -> dict:
+def training_leg(epochs: int, n: int = 2_000_000, batch: int = 4096) -> dict:
     """Training steps of the learned correction as the training loop runs
-    them: 2^20 synthetic rows (24 N(0, 1) features, N(0, 0.01) targets),
-    batches of 4,096, each epoch's 256 steps (one fused forward/backward
-    kernel and one Adam kernel each) captured in one HIP graph; the timed
-    region is `epochs` replays between HIP events on the replay stream."""
+    them on a training set of the measured dataset's size: 2,000,000
+    synthetic rows (24 N(0, 1) features, N(0, 0.01) targets), batches of
+    4,096, each epoch's 488 steps (one fused forward/backward kernel and one
+    Adam kernel each) captured in one HIP graph; the timed region is `epochs`
+    replays between HIP events on the replay stream."""
     import numpy as np
     import torch
 
@@ -542,7 +543,8 @@ def training_leg(epochs: int, n: int = 1 << 20, batch: int = 4096) -> dict:
     ms = e0.elapsed_time(e1) / steps
     tflops = TRAIN_FLOP_PER_ROW * batch / (ms * 1e-3) / 1e12
     loss = float(sur.grad[api.MLP_PARAMS].item())
-    return {"us_per_step": ms * 1e3, "rows_per_step": batch, "steps": steps, "rows_per_s": batch / (ms * 1e-3),
+    return {"us_per_step": ms * 1e3, "rows_per_step": batch, "steps": steps, "rows": n,
+            "epoch_ms": ms * len(starts), "rows_per_s": batch / (ms * 1e-3),
             "kernels": "sa_train_kernel + sa_train_adam_kernel per step, one graph per epoch",
             "flop_per_row": TRAIN_FLOP_PER_ROW, "TFLOPs": tflops, "frac_of_bf16_peak": tflops / MFMA_BF16_PEAK_TFLOPS,
             "last_loss": loss, "device_steps": int(sur.steps_dev.item())}
