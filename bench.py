@@ -422,9 +422,23 @@ def cold_leg(arch, var, cfg, plan, n_var: int, n_evals: int, steps: int, copies:
     ws = api.Workspace(plan.workspace_bytes, dev)
     ms = _graph_ms(lambda i: plan.score(arch, var, cfgs[i % copies], outputs=outs[i % copies], workspace=ws), steps)
     gbs = BYTES_PER_EVAL * n_evals / (ms * 1e-3) / 1e9
+    # the same rotation for a pure stream of the same bytes (sa_rt_stream, one
+    # launch per copy in turn, each timed alone): the cold memory ceiling
+    stream_ms = []
+    for i in range(3 * copies + 1):
+        c = cfgs[i % copies]
+        t = api.rt_stream([c["block"], c["unroll"], c["regs"], c["grid"]],
+                          [outs[i % copies]["occ"], outs[i % copies]["score"].view(torch.int32)],
+                          items=1, blocks_per_cu=0, nontemporal=True, reps=1)
+        if i > 0:
+            stream_ms.append(t)
+    sms = sum(stream_ms) / len(stream_ms)
+    sgbs = BYTES_PER_EVAL * n_evals / (sms * 1e-3) / 1e9
     return {"value": n_evals / (ms * 1e-3), "unit": "configs/s", "ms_per_step": ms, "steps": steps,
             "copies": copies, "working_set_bytes": copies * BYTES_PER_EVAL * n_evals, "GBps": gbs,
-            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "stream": {"ms": sms, "GBps": sgbs, "frac_of_hbm_peak": sgbs / HBM_PEAK_GBS, "plain_vs_stream": gbs / sgbs,
+                       "kernel": "sa_rt_stream over the same rotation, one launch per copy, each timed alone"}}
 
 
 def c2_leg(arch, steps: int) -> dict:
