@@ -243,7 +243,7 @@ def main():
     elif args.shape:
         shape = tuple(int(x) for x in args.shape.split(","))
     else:
-        shape = counted or (8192, 1, 4)
+        shape = counted or (8192, 2, 4)
     plan = api.Plan(batch.seg, k=K, shape=shape)
     ws = api.Workspace(plan.workspace_bytes, dev)
 

@@ -14,8 +14,8 @@ dispatches is kept.
 
 CLI:
   python -m paper_1701_08547_amd.counters traffic --fetch F.csv --write W.csv \\
-      --copy-fetch CF.csv --copy-write CW.csv --shape 8192,1,4 --out profiles/traffic_c1.json
-  python -m paper_1701_08547_amd.counters valu --csv V.csv --shape 8192,1,4 --out profiles/valu_c1.json
+      --copy-fetch CF.csv --copy-write CW.csv --shape 8192,2,4 --out profiles/traffic_c1.json
+  python -m paper_1701_08547_amd.counters valu --csv V.csv --shape 8192,2,4 --out profiles/valu_c1.json
 """
 from __future__ import annotations
 
