@@ -223,17 +223,26 @@ struct Evaluator {
     }
   }
 
-  // [e, pe): unaligned head and ragged tail masked, aligned body vectorised
-  // with the next chunk's loads in flight while the current one is evaluated.
-  __device__ void run(int64_t e, int64_t pe) {
+  // [e, pe) shared by nw waves, this one being wave w (nw = 1: one wave
+  // alone): the unaligned head masked by wave 0, the aligned body's chunks
+  // j = w, w + nw, ... vectorised with the next one's loads in flight while
+  // the current one is evaluated, and the ragged tail's 256-row blocks dealt
+  // out the same way.  Taking chunks in turn keeps the waves of a workgroup
+  // on adjacent addresses, as a plain stream's are: each column is read
+  // nw x 256 ITEMS contiguous bytes at a time rather than at nw fronts an
+  // nw-th of the range apart (measured faster from HBM and from the
+  // Infinity Cache alike).
+  __device__ void run(int64_t e, int64_t pe, int w = 0, int nw = 1) {
     int64_t body = e;
     if (L.vec) {
       int64_t a0 = (e + ITEMS - 1) & ~(int64_t)(ITEMS - 1);
       a0 = uniform64(a0 < pe ? a0 : pe);  // keep the chunk bases in scalar registers
-      if (a0 > e) masked(e, a0);
-      body = a0;
+      if (w == 0 && a0 > e) masked(e, a0);
       const int64_t nfull = (pe - a0) / kC;
-      if (nfull > 0) {
+      const int64_t cnt = w < nfull ? (nfull - w + nw - 1) / nw : 0;
+      if (cnt > 0) {
+        const int64_t stride = (int64_t)nw * kC;
+        const int64_t b0 = uniform64(a0 + (int64_t)w * kC);
         // Unrolled by two so that the chunk in flight and the chunk being
         // evaluated alternate between two register sets: a loop-carried copy
         // of the prefetched registers would make every iteration wait for all
@@ -241,7 +250,7 @@ struct Evaluator {
         // prefetches are unconditional (a conditional load would make the
         // compiler wait for it before evaluating); past the last chunk they
         // re-read one that is still cached.
-        Cols a = load_chunk(a0);
+        Cols a = load_chunk(b0);
         if constexpr (MODE != Mode::Keys) {
           // two dropped stores: the loop is entered with the same memory
           // operations behind the first prefetch as every later iteration
@@ -251,28 +260,29 @@ struct Evaluator {
           buf_store<ITEMS>(z, out_rsrc(nullptr, 0, 0), 4 * ITEMS * 64);
         }
         int64_t it = 0;
-        for (; it + 2 <= nfull; it += 2) {
-          const int64_t base = a0 + it * kC;
+        for (; it + 2 <= cnt; it += 2) {
+          const int64_t base = b0 + it * stride;
           if constexpr (TOPK) make_room(sel, kC, L.k, lane);
-          const Cols b = load_chunk(base + kC);
+          const Cols b = load_chunk(base + stride);
           // keep the scheduler from hoisting this chunk's first uses above
           // the prefetch: the wait for the current data can then leave the
           // prefetch (and any stores before it) in flight
           __builtin_amdgcn_sched_barrier(0);
           chunk(a, base);
           if constexpr (TOPK) make_room(sel, kC, L.k, lane);
-          a = load_chunk(it + 2 < nfull ? base + 2 * kC : base + kC);
+          a = load_chunk(it + 2 < cnt ? base + 2 * stride : base + stride);
           __builtin_amdgcn_sched_barrier(0);
-          chunk(b, base + kC);
+          chunk(b, base + stride);
         }
-        if (it < nfull) {
+        if (it < cnt) {
           if constexpr (TOPK) make_room(sel, kC, L.k, lane);
-          chunk(a, a0 + it * kC);
+          chunk(a, b0 + it * stride);
         }
-        body = a0 + nfull * kC;
       }
+      body = a0 + nfull * kC;
     }
-    for (int64_t base = body; base < pe; base += 256) masked(base, (pe - base) < 256 ? pe : base + 256);
+    for (int64_t base = body + (int64_t)w * 256; base < pe; base += (int64_t)nw * 256)
+      masked(base, (pe - base) < 256 ? pe : base + 256);
   }
 };
 
@@ -436,8 +446,9 @@ __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
 // and the workgroup holding the last one returns the counter to zero for the
 // next launch (stream-ordered launches of one plan, replayed graphs
 // included).  kind 0 items: each wave evaluates whole segments and writes
-// their rows.  kind 1 items: each wave selects over its part of one segment,
-// the parts meet in LDS and wave 0 writes the row (or the item's fragment).
+// their rows.  kind 1 items: the waves take the chunks of one segment's range
+// in turn, each selecting over its own, the selections meet in LDS and wave
+// 0 writes the row (or the item's fragment).
 template <Mode MODE, bool HAS_GRID, bool TOPK, int ITEMS, int WPB>
 __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev P) {
   extern __shared__ __align__(16) uint8_t dyn_lds[];
@@ -476,8 +487,8 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
       }
     }
     const PlanItem it = P.items[item];
-    const PlanWave pw = P.waves[item * WPB + w];
     if (it.kind == 0) {
+      const PlanWave pw = P.waves[item * WPB + w];
       const int64_t v1 = pw.v1 < L.n_var ? pw.v1 : L.n_var;
       for (int64_t v = pw.v0 > 0 ? pw.v0 : 0; v < v1; ++v) {
         const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
@@ -501,8 +512,10 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
       const int64_t v = it.v < L.n_var ? (it.v > 0 ? it.v : 0) : L.n_var - 1;
       const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
       const int64_t s1 = uniform64(clamp_off(seg[v + 1], n_evals));
-      int64_t e0 = pw.e0 > s0 ? pw.e0 : s0;
-      int64_t e1 = pw.e1 < s1 ? pw.e1 : s1;
+      // the item's range: from its first part's start to its last part's end
+      const int64_t f0 = P.waves[item * WPB].e0, f1 = P.waves[item * WPB + WPB - 1].e1;
+      const int64_t e0 = f0 > s0 ? f0 : s0;
+      const int64_t e1 = f1 < s1 ? f1 : s1;
       uint64_t mine = kKeyNone;
       if (e1 > e0) {
         Piece pc;
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
         sel.count = 0;
         sel.theta = kThetaInit;
         Evaluator<MODE, HAS_GRID, TOPK, ITEMS> ev{L, tb, pc, sel, lane};
-        ev.run(e0, e1);
+        ev.run(uniform64(e0), uniform64(e1), w, WPB);
         if constexpr (TOPK) mine = select_k(sel, k, lane);
       }
       if constexpr (TOPK) {

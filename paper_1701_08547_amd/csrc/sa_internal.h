@@ -102,17 +102,19 @@ struct KProduct {
 };
 
 // A plan cuts a CSR batch into workgroup items.  kind 0: whole segments
-// [v0, v1) per wave.  kind 1: one segment's range split into one part per
-// wave, merged in LDS; `slot` < 0 means the item covers the whole segment,
-// else its k keys go to fragment slot `slot` and a split record names the
-// slots to combine.
+// [v0, v1) per wave.  kind 1: a range of one segment, listed as one equal
+// part per wave (the first part's e0 to the last part's e1; the kernel deals
+// the range's chunks to the waves in turn, so the parts give each wave's
+// share of the work, not its rows), merged in LDS; `slot` < 0 means the item
+// covers the whole segment, else its k keys go to fragment slot `slot` and a
+// split record names the slots to combine.
 struct PlanItem {
   int32_t kind;
   int32_t slot;
   int64_t v;
 };
 struct PlanWave {
-  int64_t e0, e1;  // kind 1: evaluation range of this wave's part
+  int64_t e0, e1;  // kind 1: this wave's equal part of the item's range
   int64_t v0, v1;  // kind 0: segments of this wave
 };
 struct PlanSplit {

@@ -61,6 +61,26 @@ def test_plan_tiles_and_no_grid(tile):
     check(ref, run_plan(b, 16, (tile, 4, 4)))
 
 
+@pytest.mark.parametrize("shape", [(1024, 2, 4), (256, 4, 16)])
+def test_plan_unaligned_columns(shape):
+    """Columns at an odd offset (not 16-byte aligned) send the planned pass
+    down its masked path, where a split item's 256-row blocks are dealt to
+    its waves in turn (some waves get none): results equal the oracle's."""
+    b = workloads.custom_batch(14, [700, 5000, 33, 20000, 300], with_grid=True, name="plan-unaligned")
+    a = oracle.arch_cdna4()
+    ref = oracle.run(a, b.variants, b.configs(), k=8)
+    var, cfg = api.device_batch(b)
+    for key in ("block", "unroll", "regs", "grid"):
+        big = torch.empty(cfg[key].numel() + 1, dtype=torch.int32, device=cfg[key].device)
+        big[1:] = cfg[key]
+        cfg[key] = big[1:]
+    plan = api.Plan(b.seg, k=8, shape=shape)
+    say("plan unaligned", shape, "items", plan.n_items, "splits", plan.n_splits)
+    out = plan.score(a, var, cfg)
+    torch.cuda.synchronize()
+    check(ref, {key: t.cpu().numpy() for key, t in out.items()})
+
+
 def test_plan_optional_outputs_and_occupancy_only():
     b = workloads.custom_batch(61, SIZES, with_grid=True, name="plan-outputs")
     ref = oracle.run(oracle.arch_cdna4(), b.variants, b.configs(), k=8)
