@@ -415,9 +415,10 @@ sa_status sa_set_tile(int32_t evals_per_wave);
  *
  * A plan is a host object made once per CSR layout from a HOST copy of the
  * segment offsets.  Segments longer than `tile` are cut into workgroup items
- * of up to tile x waves_per_block evaluations, one part per wave, whose
- * per-wave top-k meet in LDS; shorter segments are packed whole into items
- * and spread over the waves.  A segment longer than one item leaves one
+ * of up to tile x waves_per_block evaluations, whose chunks the item's waves
+ * take in turn (adjacent addresses across the workgroup) and whose per-wave
+ * top-k meet in LDS; shorter segments are packed whole into items and spread
+ * over the waves.  A segment longer than one item leaves one
  * k-key fragment per item in the workspace, combined by a second small
  * kernel only when such segments exist.  Shape: tile a multiple of 256 in
  * [256, 2^20]; items_per_lane 1, 2 or 4 (consecutive evaluations per lane per
@@ -434,7 +435,7 @@ sa_status sa_set_tile(int32_t evals_per_wave);
  */
 typedef struct sa_plan sa_plan;
 typedef struct sa_plan_shape {
-  int32_t tile;            /* evaluations per wave part / per wave of packing */
+  int32_t tile;            /* evaluations per wave of an item (its share)     */
   int32_t items_per_lane;  /* 1, 2, 4                                         */
   int32_t waves_per_block; /* 4, 8, 16                                        */
 } sa_plan_shape;
