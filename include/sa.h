@@ -248,9 +248,11 @@ sa_status sa_occupancy(const sa_arch *arch, const sa_variants *variants, const s
  *             scoring kernel): score[e] receives the corrected key
  *             z = ln(score) + Delta (Delta = the network of sa_surrogate_fwd
  *             on the 24 features of sa_features, +inf when illegal) and the
- *             top-k ranks by z with the same tie rule.  Its weight pointers
- *             must be 16-byte aligned (SA_ERR_ALIGN otherwise); every one of
- *             them is required.
+ *             top-k ranks by z with the same tie rule.  W1 and W2 must be
+ *             8-byte aligned and w3 2-byte aligned (SA_ERR_ALIGN otherwise;
+ *             16-byte aligned W1 and W2 are staged a whole 16 bytes at a
+ *             time, others element by element, to the same result); every
+ *             pointer is required.
  *   workspace device buffer of sa_workspace_bytes(...) bytes (may be NULL
  *             when no top-k is asked for).  Contents need no initialisation.
  *             Segments that span several wave-tiles leave per-tile partial

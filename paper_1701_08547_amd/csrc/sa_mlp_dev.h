@@ -96,12 +96,14 @@ typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double gelu_exact(double a) { return 0.5 * a * erfc(-a * 0.70710678118654752440); }
 
-// (g0, g1) of piece i, from the binary64 GELU at its ends.
-__device__ __forceinline__ f32x2_t gelu_piece(int i) {
+// Binary64 GELU at the edge a_i = (i - 512) / 64 of pieces i - 1 and i.
+__device__ __forceinline__ double gelu_edge(int i) { return gelu_exact((double)(i - 512) / 64.0); }
+
+// (g0, g1) of piece i, from the binary64 GELU at its ends y0 = gelu_edge(i)
+// and y1 = gelu_edge(i + 1) (not read for the first and last piece).
+__device__ __forceinline__ f32x2_t gelu_piece(int i, double y0, double y1) {
   if (i <= 0) return f32x2_t{0.0f, 0.0f};
   if (i >= kGeluN - 1) return f32x2_t{-kTOrigin / kTScale, 1.0f / kTScale};
-  const double a0 = (double)(i - 512) / 64.0, a1 = (double)(i + 1 - 512) / 64.0;
-  const double y0 = gelu_exact(a0), y1 = gelu_exact(a1);
   const double g1 = (y1 - y0) * kGeluN;  // per unit of u
   return f32x2_t{(float)(y0 - (double)i / kGeluN * g1), (float)g1};
 }
@@ -197,7 +199,10 @@ struct __align__(16) MlpLdsT {
   uint16_t W2[kMH * kLdW2];  // W2[o][.] / 16, columns permuted per 32-wide chunk (see w2_column)
   uint16_t w3p[kMH];         // w3 in the same permuted order
   float b2[kMH];             // b2 / 16 + 1/2 (b1 is folded into W1, see load_weights_t)
-  f32x2_t gelu[kGeluN];      // pieces (g0, g1)
+  union {
+    f32x2_t gelu[kGeluN];    // pieces (g0, g1)
+    double edge[kGeluN];     // while staging: GELU at the inner piece edges
+  };
   float mean[kMF], inv_std[kMF];
   float b3;
 };
@@ -233,24 +238,70 @@ __device__ __forceinline__ uint16_t bf16_scaled(uint16_t b) {
 __device__ __forceinline__ uint16_t bf16_rn(float x) { return (uint16_t)(pack_bf16(x, 0.0f) & 0xFFFFu); }
 __device__ __forceinline__ float bf16_value(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
+// Two bfloat16 (low half first) times kTScale each.
+__device__ __forceinline__ uint32_t bf16x2_scaled(uint32_t u) {
+  return (uint32_t)bf16_scaled((uint16_t)(u & 0xFFFFu)) | ((uint32_t)bf16_scaled((uint16_t)(u >> 16)) << 16);
+}
+__device__ __forceinline__ u32x4_t bf16x8_scaled(u32x4_t x) {
+  return u32x4_t{bf16x2_scaled(x[0]), bf16x2_scaled(x[1]), bf16x2_scaled(x[2]), bf16x2_scaled(x[3])};
+}
+
+// The first layer's scaled bias for hidden unit h as its three bfloat16
+// parts hi, mid, lo (hi + mid + lo = b1 / 16 + 1/2 exactly).
+__device__ __forceinline__ void bias_split(const MlpDev &M, int h, uint16_t &hi, uint16_t &mid, uint16_t &lo) {
+  const float v = fmaf(M.b1[h], kTScale, kTOrigin);
+  hi = bf16_rn(v);
+  const float r1 = v - bf16_value(hi);
+  mid = bf16_rn(r1);
+  lo = bf16_rn(r1 - bf16_value(mid));
+}
+
+// Staging of the weights in LDS.  With 16-byte aligned weight arrays (the
+// usual case) every thread moves whole 16-byte pieces, all of its loads in
+// flight at once: a W1 row is four pieces (the last one's first three slots
+// take the bias split), a W2 row sixteen, each splitting into two 4-column
+// runs whose positions w2_column permutes as a whole (run a of a 32-wide
+// chunk, columns 32 c + 4 a .. + 3, lands at 32 c + 8 (a mod 4) + 4 (a / 4)).
+// Otherwise element by element, to the same result.
 __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthreads) {
-  for (int i = tid; i < kMH * kMK; i += nthreads) {
-    const int k = i % kMK;
-    if (k >= kMF && k < kMF + 3) continue;
-    s.W1[(i / kMK) * kLdW1 + k] = bf16_scaled(M.W1[i]);
-  }
-  for (int i = tid; i < kMH; i += nthreads) {
-    const float v = fmaf(M.b1[i], kTScale, kTOrigin);
-    const uint16_t hi = bf16_rn(v);
-    const float r1 = v - bf16_value(hi);
-    const uint16_t mid = bf16_rn(r1);
-    s.W1[i * kLdW1 + kMF] = hi;
-    s.W1[i * kLdW1 + kMF + 1] = mid;
-    s.W1[i * kLdW1 + kMF + 2] = bf16_rn(r1 - bf16_value(mid));
-  }
-  for (int i = tid; i < kMH * kMH; i += nthreads) {
-    const int o = i / kMH, p = i % kMH;
-    s.W2[o * kLdW2 + p] = bf16_scaled(M.W2[o * kMH + w2_column(p)]);
+  const bool vec = (((uintptr_t)M.W1 | (uintptr_t)M.W2) & 15u) == 0;
+  if (vec) {
+    for (int i = tid; i < kMH * (kMK / 8); i += nthreads) {
+      const int h = i / (kMK / 8), m = i % (kMK / 8);
+      u32x4_t x = bf16x8_scaled(*(const u32x4_t *)(M.W1 + h * kMK + 8 * m));
+      if (8 * m == kMF) {
+        uint16_t hi, mid, lo;
+        bias_split(M, h, hi, mid, lo);
+        x[0] = (uint32_t)hi | ((uint32_t)mid << 16);
+        x[1] = (uint32_t)lo | (x[1] & 0xFFFF0000u);
+      }
+      *(u32x4_t *)(s.W1 + h * kLdW1 + 8 * m) = x;
+    }
+    typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+    for (int i = tid; i < kMH * (kMH / 8); i += nthreads) {
+      const int o = i / (kMH / 8), m = i % (kMH / 8), a0 = 2 * (m & 3), a1 = a0 + 1;
+      const u32x4_t x = bf16x8_scaled(*(const u32x4_t *)(M.W2 + o * kMH + 8 * m));
+      uint16_t *row = s.W2 + o * kLdW2 + 32 * (m >> 2);
+      *(u32x2_t *)(row + 8 * (a0 & 3) + 4 * (a0 >> 2)) = u32x2_t{x[0], x[1]};
+      *(u32x2_t *)(row + 8 * (a1 & 3) + 4 * (a1 >> 2)) = u32x2_t{x[2], x[3]};
+    }
+  } else {
+    for (int i = tid; i < kMH * kMK; i += nthreads) {
+      const int k = i % kMK;
+      if (k >= kMF && k < kMF + 3) continue;
+      s.W1[(i / kMK) * kLdW1 + k] = bf16_scaled(M.W1[i]);
+    }
+    for (int i = tid; i < kMH; i += nthreads) {
+      uint16_t hi, mid, lo;
+      bias_split(M, i, hi, mid, lo);
+      s.W1[i * kLdW1 + kMF] = hi;
+      s.W1[i * kLdW1 + kMF + 1] = mid;
+      s.W1[i * kLdW1 + kMF + 2] = lo;
+    }
+    for (int i = tid; i < kMH * kMH; i += nthreads) {
+      const int o = i / kMH, p = i % kMH;
+      s.W2[o * kLdW2 + p] = bf16_scaled(M.W2[o * kMH + w2_column(p)]);
+    }
   }
   for (int i = tid; i < kMH; i += nthreads) {
     s.b2[i] = fmaf(M.b2[i], kTScale, kTOrigin);
@@ -260,7 +311,25 @@ __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthread
     s.mean[i] = M.mean[i];
     s.inv_std[i] = M.inv_std[i];
   }
-  for (int i = tid; i < kGeluN; i += nthreads) s.gelu[i] = gelu_piece(i);
+  // GELU pieces: each inner edge's value once (binary64, held in the table's
+  // own storage), then every piece from its two edges.  nthreads >= 256.
+  for (int i = 1 + tid; i < kGeluN; i += nthreads) s.edge[i] = gelu_edge(i);
+  __syncthreads();
+  f32x2_t piece[kGeluN / 256];
+#pragma unroll
+  for (int r = 0; r < kGeluN / 256; ++r) {
+    const int i = tid + r * nthreads;
+    if (i < kGeluN) {
+      const bool inner = i > 0 && i < kGeluN - 1;
+      piece[r] = gelu_piece(i, inner ? s.edge[i] : 0.0, inner ? s.edge[i + 1] : 0.0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kGeluN / 256; ++r) {
+    const int i = tid + r * nthreads;
+    if (i < kGeluN) s.gelu[i] = piece[r];
+  }
   if (tid == 0) s.b3 = M.b3[0];
 }
 

@@ -134,6 +134,34 @@ def test_forward_trained_scale_weights():
     assert (np.abs(got - want) / (1.0 + np.abs(want))).max() <= 2 ** -7
 
 
+def test_weights_not_16_byte_aligned():
+    """Weight arrays 8- but not 16-byte aligned take the element-by-element
+    staging: Delta (sa_surrogate_fwd) and the corrected pass's keys and
+    selections (sa_score with the network) equal those of aligned arrays
+    bit for bit."""
+    arch = oracle.arch_cdna4()
+    b = feature_batch(23, [3000, 700, 5000])
+    f = oracle_features(b, arch)[legal_mask(b, arch)]
+    p, mean, inv, s = surrogate(6, f)
+    feat = torch.from_numpy(f).cuda()
+    var, cfg = api.device_batch(b)
+    want_d = s.forward(feat).cpu().numpy()
+    want = api.score(arch, var, cfg, k=8, mlp=s)
+    for name in ("W1", "W2"):
+        t = getattr(s, name)
+        u = torch.empty(t.numel() + 4, dtype=t.dtype, device=t.device)[4:].view(t.shape)
+        u.copy_(t)
+        assert u.data_ptr() % 16 == 8
+        setattr(s, name, u)
+    say("unaligned weights", s.W1.data_ptr() % 16, s.W2.data_ptr() % 16)
+    got_d = s.forward(feat).cpu().numpy()
+    got = api.score(arch, var, cfg, k=8, mlp=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(want_d.view(np.uint32), got_d.view(np.uint32))
+    for key in ("score", "idx", "val", "occ"):
+        assert np.array_equal(want[key].cpu().numpy(), got[key].cpu().numpy()), key
+
+
 def _grads_flat(grad):
     g = api.params_from_flat(grad)
     return {k: np.asarray(g[k], np.float64).reshape(-1) for k in NAMES}
