@@ -33,11 +33,21 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
-// Sum over the 16 lanes of a lane group (lanes with equal l / 16).
+// Sum over the 16 lanes of a lane group (lanes with equal l / 16), left in
+// every lane of the group: four additions of the value rotated within the
+// row by 8, 4, 2 and 1 lanes (DPP row_ror, no LDS traffic).  After the
+// rotation by 2^s every lane holds the sum over the lanes congruent to it
+// modulo 2^s, the same pairs of partial sums a butterfly over lane l xor 2^s
+// adds, so the result is the butterfly's bit for bit.
+template <int CTRL>
+__device__ __forceinline__ float row_ror_add(float v) {
+  return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ float sum16(float v) {
-#pragma unroll
-  for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
-  return v;
+  v = row_ror_add<0x128>(v);  // row_ror:8
+  v = row_ror_add<0x124>(v);  // row_ror:4
+  v = row_ror_add<0x122>(v);  // row_ror:2
+  return row_ror_add<0x121>(v);  // row_ror:1
 }
 
 // ---------------------------------------------------------------- features
@@ -471,8 +481,9 @@ __global__ __launch_bounds__(256) void sa_train_rank_kernel(const float *feat, c
 
 // Sum the workgroups' partials (fixed order: deterministic), then Adam on the
 // fp32 master weights and the bf16 shadow.  A workgroup takes 64 parameters:
-// each of its four waves adds every fourth partial (4 loads in flight per
-// lane), and the four sums are added in wave order.  With a step counter,
+// each of its four waves adds every fourth partial (into four running sums,
+// up to 16 loads in flight per lane), and the four sums are added in wave
+// order.  With a step counter,
 // the bias corrections follow the count the training kernel has just
 // advanced.
 constexpr int kAdamParams = 64;
@@ -482,10 +493,19 @@ __global__ __launch_bounds__(256) void sa_train_adam_kernel(TrainState S, MlpDev
   __shared__ float red[4][kAdamParams];
   const int j = threadIdx.x & (kAdamParams - 1), wv = threadIdx.x / kAdamParams;
   const int64_t i = (int64_t)blockIdx.x * kAdamParams + j;
+  // the bias corrections first (wave 0 applies the update): their binary64
+  // powers then overlap the partials' loads instead of following the barrier
+  float bc1 = h.bc1, bc2 = h.bc2;
+  if (h.step_counter && wv == 0) {
+    const double t = (double)*h.step_counter;
+    bc1 = (float)(1.0 - pow(h.beta1_d, t));
+    bc2 = (float)(1.0 - pow(h.beta2_d, t));
+  }
   float g = 0.0f;
   if (i < kPartStride) {
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     int64_t p = wv;
+#pragma unroll 4
     for (; p + 12 < n_parts; p += 16) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[u] += part[(p + 4 * u) * kPartStride + i];
@@ -499,12 +519,6 @@ __global__ __launch_bounds__(256) void sa_train_adam_kernel(TrainState S, MlpDev
   g = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
   if (grad_out) grad_out[i] = i == kPartLoss ? g * h.inv_n : g;
   if (i >= kPartUsed) return;
-  float bc1 = h.bc1, bc2 = h.bc2;
-  if (h.step_counter) {
-    const double t = (double)*h.step_counter;
-    bc1 = (float)(1.0 - pow(h.beta1_d, t));
-    bc2 = (float)(1.0 - pow(h.beta2_d, t));
-  }
   const float m = h.beta1 * S.m[i] + (1.0f - h.beta1) * g;
   const float v = h.beta2 * S.v[i] + (1.0f - h.beta2) * g * g;
   S.m[i] = m;
