@@ -204,27 +204,10 @@ __global__ __launch_bounds__(kTrainThreads) void sa_train_kernel(MlpDev M, const
   __shared__ TrainLds s;
   const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
   const int r = lane & 15, q = lane >> 4;
-  load_weights_t(M, s.f, tid, kTrainThreads);
+  // the backward's W2 staged beside the forward's: W2b[k][p] = W2[w2_column(p)][k]
+  load_weights_t(M, s.f, tid, kTrainThreads, s.W2b);
   for (int i = tid; i < kMH; i += kTrainThreads) s.w3[i] = bf2f(M.w3[i]);
   if (step_counter && blockIdx.x == 0 && tid == 0) *step_counter += 1;  // read by the update kernel
-  __syncthreads();
-  // the backward's W2 from the forward's staged copy (W2 / 16, columns
-  // permuted): W2b[k][p] = W2[w2_column(p)][k] = 16 staged[w2_column(p)][w2_position(k)],
-  // eight positions p = 8 m .. 8 m + 7 (rows 32 c + 4 q + 0..3 and
-  // 32 c + 16 + 4 q + 0..3 of W2, c = m / 4, q = m mod 4) per 16-byte store
-  for (int i = tid; i < kMH * (kMH / 8); i += kTrainThreads) {
-    const int k = i / (kMH / 8), m = i % (kMH / 8);
-    const int o0 = 32 * (m >> 2) + 4 * (m & 3), kp = w2_position(k);
-    uint32_t h[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int o = o0 + (j < 4 ? j : 12 + j);
-      const float v = bf2f(s.f.W2[o * kLdW2 + kp]) * (1.0f / kTScale);
-      h[j] = __float_as_uint(v) >> 16;
-    }
-    *(u32x4_t *)(s.W2b + k * kLdW2 + 8 * m) =
-        u32x4_t{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
-  }
   __syncthreads();
   const float inv_n2 = 2.0f / (float)n;
   // per-lane running sums over this workgroup's rows (reduced at the end)

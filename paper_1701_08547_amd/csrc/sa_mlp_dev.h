@@ -262,8 +262,12 @@ __device__ __forceinline__ void bias_split(const MlpDev &M, int h, uint16_t &hi,
 // take the bias split), a W2 row sixteen, each splitting into two 4-column
 // runs whose positions w2_column permutes as a whole (run a of a 32-wide
 // chunk, columns 32 c + 4 a .. + 3, lands at 32 c + 8 (a mod 4) + 4 (a / 4)).
-// Otherwise element by element, to the same result.
-__device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthreads) {
+// Otherwise element by element, to the same result.  With W2t (training's
+// backward), W2 is also written there transposed, unscaled and with its rows
+// permuted as the forward's columns are: W2t[k][w2_position(o)] = W2[o][k]
+// (rows of kLdW2 elements), each loaded piece's eight values stored at once
+// from the same registers.
+__device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthreads, uint16_t *W2t = nullptr) {
   const bool vec = (((uintptr_t)M.W1 | (uintptr_t)M.W2) & 15u) == 0;
   if (vec) {
     for (int i = tid; i < kMH * (kMK / 8); i += nthreads) {
@@ -280,10 +284,16 @@ __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthread
     typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
     for (int i = tid; i < kMH * (kMH / 8); i += nthreads) {
       const int o = i / (kMH / 8), m = i % (kMH / 8), a0 = 2 * (m & 3), a1 = a0 + 1;
-      const u32x4_t x = bf16x8_scaled(*(const u32x4_t *)(M.W2 + o * kMH + 8 * m));
+      const u32x4_t raw = *(const u32x4_t *)(M.W2 + o * kMH + 8 * m);
+      const u32x4_t x = bf16x8_scaled(raw);
       uint16_t *row = s.W2 + o * kLdW2 + 32 * (m >> 2);
       *(u32x2_t *)(row + 8 * (a0 & 3) + 4 * (a0 >> 2)) = u32x2_t{x[0], x[1]};
       *(u32x2_t *)(row + 8 * (a1 & 3) + 4 * (a1 >> 2)) = u32x2_t{x[2], x[3]};
+      if (W2t) {
+        uint16_t *col = W2t + 8 * m * kLdW2 + w2_position(o);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) col[j * kLdW2] = (uint16_t)(raw[j >> 1] >> (16 * (j & 1)));
+      }
     }
   } else {
     for (int i = tid; i < kMH * kMK; i += nthreads) {
@@ -301,6 +311,7 @@ __device__ void load_weights_t(const MlpDev &M, MlpLdsT &s, int tid, int nthread
     for (int i = tid; i < kMH * kMH; i += nthreads) {
       const int o = i / kMH, p = i % kMH;
       s.W2[o * kLdW2 + p] = bf16_scaled(M.W2[o * kMH + w2_column(p)]);
+      if (W2t) W2t[p * kLdW2 + w2_position(o)] = M.W2[o * kMH + p];
     }
   }
   for (int i = tid; i < kMH; i += nthreads) {
