@@ -248,12 +248,17 @@ __global__ __launch_bounds__(kTrainThreads) void sa_train_kernel(MlpDev M, const
     // network's zeros there)
     if (q == 3) xb = u32x4_t{kOnes24, kOnes26, 0u, 0u};
     // layer 1 (scaled pre-activations kept for the backward pass)
+    // (each layer's contractions all issued before its GELU: the pre-activations
+    // are kept for the backward pass anyway)
     f32x4_t t1[8];
     uint32_t h1[8][2];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const u32x4_t a = *(const u32x4_t *)(s.f.W1 + (16 * t + r) * kLdW1 + 8 * q);
       t1[t] = mfma32(a, xb, f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
       float v[4] = {t1[t][0], t1[t][1], t1[t][2], t1[t][3]};
       gelu_t_n<4>(v, s.f.gelu);
       h1[t][0] = pack_bf16(v[0], v[1]);
@@ -274,7 +279,10 @@ __global__ __launch_bounds__(kTrainThreads) void sa_train_kernel(MlpDev M, const
         acc = mfma32(a, u32x4_t{h1[2 * c][0], h1[2 * c][1], h1[2 * c + 1][0], h1[2 * c + 1][1]}, acc);
       }
       t2[ot] = acc;
-      float v[4] = {acc[0], acc[1], acc[2], acc[3]};
+    }
+#pragma unroll
+    for (int ot = 0; ot < 8; ++ot) {
+      float v[4] = {t2[ot][0], t2[ot][1], t2[ot][2], t2[ot][3]};
       gelu_t_n<4>(v, s.f.gelu);
       h2[ot][0] = pack_bf16(v[0], v[1]);
       h2[ot][1] = pack_bf16(v[2], v[3]);
