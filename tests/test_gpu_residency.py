@@ -40,7 +40,8 @@ CASES = [(64, 64, 0), (64, 72, 0), (64, 80, 0), (64, 128, 0), (64, 256, 0), (64,
          (192, 16, 0), (192, 168, 0), (320, 16, 0), (320, 96, 0), (384, 16, 0), (384, 128, 0), (448, 16, 0),
          (576, 16, 0), (640, 16, 0), (768, 16, 0), (960, 16, 0)]
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# directory that receives the probe record (device descriptor and every case), when set
+OUT = os.environ.get("SA_RESIDENCY_RECORD")
 
 
 def say(*a):
@@ -68,9 +69,10 @@ def results(device_arch):
         r.pop("per_cu")
         say(json.dumps(r, sort_keys=True))
         got.append(r)
-    os.makedirs(OUT, exist_ok=True)
-    with open(os.path.join(OUT, "residency_probe.json"), "w") as f:
-        json.dump({"device_arch": device_arch, "cases": got}, f, indent=1, sort_keys=True)
+    if OUT:
+        os.makedirs(OUT, exist_ok=True)
+        with open(os.path.join(OUT, "residency_probe.json"), "w") as f:
+            json.dump({"device_arch": device_arch, "cases": got}, f, indent=1, sort_keys=True)
     return got
 
 

@@ -1,6 +1,6 @@
 """The static-vs-dynamic instruction-mix comparison (Sec. IV-B's error rates of
 the instruction-mix metrics, the analog of its Table II check) recomputed on
-the host: the static side from this build's own gfx950 assembly of the
+the host: the static side from the library's own gfx950 assembly of the
 measured kernel families, the dynamic side from the committed per-dispatch SQ
 counter table of one rocprofv3 run; the error table in the profile summary
 must be what these two give."""
