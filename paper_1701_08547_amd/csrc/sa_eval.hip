@@ -450,7 +450,9 @@ __global__ __launch_bounds__(kBlockThreads) void sa_merge_kernel(EvalLaunch L) {
 // in turn, each selecting over its own, the selections meet in LDS and wave
 // 0 writes the row (or the item's fragment).
 template <Mode MODE, bool HAS_GRID, bool TOPK, int ITEMS, int WPB>
-__global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev P) {
+// (at most 128 registers: four waves per SIMD at every shape that fits them)
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) void sa_plan_kernel(EvalLaunch L,
+                                                                                                   PlanDev P) {
   extern __shared__ __align__(16) uint8_t dyn_lds[];
   __shared__ float tab_rcap[kMaxWB + 1];
   __shared__ uint32_t tab_mwb[kMaxWB + 2];
@@ -538,17 +540,33 @@ __global__ __launch_bounds__(64 * WPB) void sa_plan_kernel(EvalLaunch L, PlanDev
       if (w == 0) {
         const int64_t v = it.v < L.n_var ? (it.v > 0 ? it.v : 0) : L.n_var - 1;
         const int64_t s0 = uniform64(clamp_off(seg[v], n_evals));
-        sel.count = 0;
-        sel.theta = kThetaInit;
-        for (int base = 0; base < WPB * k; base += 64) {
-          const int j = base + lane;
-          const uint64_t key = j < WPB * k ? wgk[j / k][j % k] : kKeyNone;
-          make_room(sel, 64, k, lane);
-          const bool cand[1] = {key != kKeyNone && (uint32_t)(key >> 32) <= sel.theta};
-          const uint64_t keys1[1] = {key};
-          offer<1>(sel, cand, keys1);
+        // The waves' lists are sorted (kKeyNone last) and their keys distinct
+        // (local indices), so a key's place among all of them is its place in
+        // its own list plus the keys below it in each other list (a lower
+        // bound by bisection); the keys placed below k are the item's k
+        // smallest, in order.  Wave 0's candidate buffer is free to hold them.
+        uint64_t *out = sel.buf;
+        if (lane < k) out[lane] = kKeyNone;
+        wave_lds_sync();
+        for (int j = lane; j < WPB * k; j += 64) {
+          const int a = j / k, r = j - a * k;
+          const uint64_t key = wgk[a][r];
+          if (key == kKeyNone) continue;
+          int place = r;
+#pragma unroll 1
+          for (int b = 0; b < WPB; ++b) {
+            if (b == a) continue;
+            int lo = 0, hi = k;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (wgk[b][mid] < key) lo = mid + 1; else hi = mid;
+            }
+            place += lo;
+          }
+          if (place < k) out[place] = key;
         }
-        const uint64_t m = select_k(sel, k, lane);
+        wave_lds_sync();
+        const uint64_t m = lane < k ? out[lane] : kKeyNone;
         if (it.slot < 0) {
           write_final(m, k, lane, v, L.topk_idx, L.topk_val, MODE == Mode::Keys ? L.keys : nullptr, s0);
         } else if (lane < k) {
